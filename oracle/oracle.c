@@ -1,0 +1,471 @@
+/*
+ * Float-float reference oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, scalar CPU implementation of the float-float operators of
+ * Da Graca & Defour, "Implementation of float-float operators on graphics
+ * hardware" (cs/0603115).  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library; the product path
+ * (the HIP library) never does, and the two share no code.
+ *
+ * Arithmetic model.  Every operation written below as a C float operation is
+ * ONE IEEE-754 binary32 operation rounded to nearest-even: this file must be
+ * built with SSE floating point (x86-64 default, FLT_EVAL_METHOD == 0),
+ * -ffp-contract=off and without -ffast-math, and runs with the default MXCSR
+ * (subnormals neither flushed nor treated as zero).  The paper writes these
+ * rounded operations as (+), (-), (x), (/) (section 4.1); its proofs assume
+ * faithful rounding with a guard bit, which round-to-nearest satisfies.
+ * The only fused operation is fmaf(), used solely by the FMA form of TwoProd.
+ *
+ * Readings of the paper taken here (each one is listed in the design notes):
+ *   - Add12 everywhere is the branch-free six-operation form (section 4
+ *     prefers it; section 4.1, Add12 theorem).
+ *   - Mul22's final step renormalises (t1, t3): the printed Add12(t1, t2)
+ *     leaves t3 unused, a typo (section 4.1, Mul22 theorem).
+ *   - Division is not defined by the paper: Div22 follows Dekker's div2
+ *     (Dekker 1971, the paper's reference for Split and Mul12), with a
+ *     correctly rounded binary32 quotient and Add12 as the final step.
+ *   - Reductions accumulate exact products with Add22, in index order.
+ *
+ * Exact references (dot products, GEMM entries, gradients) do not round at
+ * all: a long fixed-point accumulator adds every exact FP32xFP32 product.
+ *
+ * Parity pins: every function here is checked by the CPU test-suite against
+ * exact rational arithmetic, closed forms or the paper's error bounds; see the
+ * per-function comments.
+ */
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#if !defined(FLT_EVAL_METHOD) || FLT_EVAL_METHOD != 0
+#error "the oracle needs binary32 evaluation (SSE), not extended precision"
+#endif
+
+#pragma STDC FP_CONTRACT OFF
+
+#define ORACLE_ABI_VERSION 1
+
+int oracle_abi_version(void) { return ORACLE_ABI_VERSION; }
+
+/* ------------------------------------------------------------------------ */
+/* Error-free transformations (section 4.1)                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Add12 theorem (Knuth): s = a (+) b and r with s + r = a + b exactly.
+ * Six rounded operations, no branch. */
+static void add12(float a, float b, float *s_out, float *r_out)
+{
+    float s = a + b;
+    float v = s - a;
+    float r = (a - (s - v)) + (b - v);
+    *s_out = s;
+    *r_out = r;
+}
+
+/* The "one test" Add12 the paper mentions next to the branch-free one
+ * (section 4): Fast2Sum, exact when |a| >= |b|. Kept as a reference variant;
+ * no operator below uses it. */
+static void fast_add12(float a, float b, float *s_out, float *r_out)
+{
+    float s = a + b;
+    float z = s - a;
+    *s_out = s;
+    *r_out = b - z;
+}
+
+/* Split theorem (Dekker): p = 24, splitting point s = 12, constant 2^12 + 1. */
+static void split(float a, float *hi_out, float *lo_out)
+{
+    const float c_split = 4097.0f; /* 2^12 (+) 1, exact */
+    float c = c_split * a;
+    float a_big = c - a;
+    float a_hi = c - a_big;
+    float a_lo = a - a_hi;
+    *hi_out = a_hi;
+    *lo_out = a_lo;
+}
+
+/* Mul12 theorem (Dekker): x = a (x) b and the error y, with a*b = x + y. */
+static void mul12_dekker(float a, float b, float *x_out, float *y_out)
+{
+    float x = a * b;
+    float ah, al, bh, bl;
+    split(a, &ah, &al);
+    split(b, &bh, &bl);
+    float err1 = x - (ah * bh);
+    float err2 = err1 - (al * bh);
+    float err3 = err2 - (ah * bl);
+    float y = (al * bl) - err3;
+    *x_out = x;
+    *y_out = y;
+}
+
+/* TwoProd with one fused multiply-add (not in the paper; same contract as
+ * Mul12): y = fma(a, b, -x) is the exact error of x = a (x) b whenever that
+ * error is representable. */
+static void mul12_fma(float a, float b, float *x_out, float *y_out)
+{
+    float x = a * b;
+    *x_out = x;
+    *y_out = fmaf(a, b, -x);
+}
+
+static void mul12(float a, float b, int use_dekker, float *x, float *y)
+{
+    if (use_dekker)
+        mul12_dekker(a, b, x, y);
+    else
+        mul12_fma(a, b, x, y);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Float-float operators (section 4.1, Add22 and Mul22 theorems; Div22 from   */
+/* Dekker's div2)                                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Add22 theorem: the sum of two float-float numbers, branch on |ah| >= |bh|,
+ * each chain evaluated left to right as parenthesised in the paper. */
+static void add22(float ah, float al, float bh, float bl, float *rh, float *rl)
+{
+    float r = ah + bh;
+    float s;
+    if (fabsf(ah) >= fabsf(bh))
+        s = (((ah - r) + bh) + bl) + al;
+    else
+        s = (((bh - r) + ah) + al) + bl;
+    add12(r, s, rh, rl);
+}
+
+/* Sub22: Add22 with the second operand negated (negation is exact). */
+static void sub22(float ah, float al, float bh, float bl, float *rh, float *rl)
+{
+    add22(ah, al, -bh, -bl, rh, rl);
+}
+
+/* Mul22 theorem, with the final renormalisation of (t1, t3). */
+static void mul22(float ah, float al, float bh, float bl, int use_dekker,
+                  float *rh, float *rl)
+{
+    float t1, t2;
+    mul12(ah, bh, use_dekker, &t1, &t2);
+    float t3 = ((ah * bl) + (al * bh)) + t2;
+    add12(t1, t3, rh, rl);
+}
+
+/* Div22 after Dekker's div2: c = ah / bh; (u, uu) = c * bh exactly;
+ * cc = ((((ah - u) - uu) + al) - c*bl) / bh; result = Add12(c, cc). */
+static void div22(float ah, float al, float bh, float bl, int use_dekker,
+                  float *rh, float *rl)
+{
+    float c = ah / bh;
+    float u, uu;
+    mul12(c, bh, use_dekker, &u, &uu);
+    float t = (((ah - u) - uu) + al) - (c * bl);
+    float cc = t / bh;
+    add12(c, cc, rh, rl);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Array entry points: one scalar loop each, element i independent.         */
+/* ------------------------------------------------------------------------ */
+
+void oracle_add12(const float *a, const float *b, float *s, float *r, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        add12(a[i], b[i], &s[i], &r[i]);
+}
+
+void oracle_fast_add12(const float *a, const float *b, float *s, float *r,
+                       int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        fast_add12(a[i], b[i], &s[i], &r[i]);
+}
+
+void oracle_split(const float *a, float *hi, float *lo, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        split(a[i], &hi[i], &lo[i]);
+}
+
+void oracle_mul12(const float *a, const float *b, float *x, float *y, int64_t n,
+                  int use_dekker)
+{
+    for (int64_t i = 0; i < n; ++i)
+        mul12(a[i], b[i], use_dekker, &x[i], &y[i]);
+}
+
+void oracle_add22(const float *ah, const float *al, const float *bh,
+                  const float *bl, float *rh, float *rl, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        add22(ah[i], al[i], bh[i], bl[i], &rh[i], &rl[i]);
+}
+
+void oracle_sub22(const float *ah, const float *al, const float *bh,
+                  const float *bl, float *rh, float *rl, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        sub22(ah[i], al[i], bh[i], bl[i], &rh[i], &rl[i]);
+}
+
+void oracle_mul22(const float *ah, const float *al, const float *bh,
+                  const float *bl, float *rh, float *rl, int64_t n,
+                  int use_dekker)
+{
+    for (int64_t i = 0; i < n; ++i)
+        mul22(ah[i], al[i], bh[i], bl[i], use_dekker, &rh[i], &rl[i]);
+}
+
+void oracle_div22(const float *ah, const float *al, const float *bh,
+                  const float *bl, float *rh, float *rl, int64_t n,
+                  int use_dekker)
+{
+    for (int64_t i = 0; i < n; ++i)
+        div22(ah[i], al[i], bh[i], bl[i], use_dekker, &rh[i], &rl[i]);
+}
+
+/* Elementwise op selected by code: 0 add, 1 sub, 2 mul (FMA TwoProd),
+ * 3 mul (Dekker TwoProd), 4 div (FMA TwoProd).  Used by the benchmark's CPU
+ * leg so that one call times one operator over a sample. */
+int oracle_elementwise(int op, const float *ah, const float *al,
+                       const float *bh, const float *bl, float *rh, float *rl,
+                       int64_t n)
+{
+    switch (op) {
+    case 0: oracle_add22(ah, al, bh, bl, rh, rl, n); return 0;
+    case 1: oracle_sub22(ah, al, bh, bl, rh, rl, n); return 0;
+    case 2: oracle_mul22(ah, al, bh, bl, rh, rl, n, 0); return 0;
+    case 3: oracle_mul22(ah, al, bh, bl, rh, rl, n, 1); return 0;
+    case 4: oracle_div22(ah, al, bh, bl, rh, rl, n, 0); return 0;
+    default: return -1;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Float-float accumulation in index order (reductions, matvec, plain GEMM) */
+/* ------------------------------------------------------------------------ */
+
+/* dot of FP32 vectors: acc = Add22(acc, TwoProd_fma(x_i, y_i)), i ascending. */
+void oracle_dot_seq(const float *x, const float *y, int64_t n, float *out2)
+{
+    float acc_h = 0.0f, acc_l = 0.0f;
+    for (int64_t i = 0; i < n; ++i) {
+        float p, e;
+        mul12_fma(x[i], y[i], &p, &e);
+        add22(acc_h, acc_l, p, e, &acc_h, &acc_l);
+    }
+    out2[0] = acc_h;
+    out2[1] = acc_l;
+}
+
+/* dot of float-float vectors with strides:
+ * acc = Add22(acc, Mul22(x_i, y_i)), i ascending (FMA TwoProd). */
+void oracle_dot_ff_seq(const float *xh, const float *xl, int64_t incx,
+                       const float *yh, const float *yl, int64_t incy,
+                       int64_t n, float *out2)
+{
+    float acc_h = 0.0f, acc_l = 0.0f;
+    for (int64_t i = 0; i < n; ++i) {
+        float ph, pl;
+        mul22(xh[i * incx], xl[i * incx], yh[i * incy], yl[i * incy], 0, &ph,
+              &pl);
+        add22(acc_h, acc_l, ph, pl, &acc_h, &acc_l);
+    }
+    out2[0] = acc_h;
+    out2[1] = acc_l;
+}
+
+/* Plain float-float GEMM on the block rows [i0,i1) x cols [j0,j1) of
+ * C = A*B (row-major): C_ij = Add22-accumulation over k ascending of
+ * Mul22(A_ik, B_kj), starting from (0, 0).  The block is stored at
+ * C[(i - i0) * ldc + (j - j0)]. */
+void oracle_gemm_ff_seq(int64_t K, const float *Ah, const float *Al, int64_t lda,
+                        const float *Bh, const float *Bl, int64_t ldb, float *Ch,
+                        float *Cl, int64_t ldc, int64_t i0, int64_t i1,
+                        int64_t j0, int64_t j1)
+{
+    for (int64_t i = i0; i < i1; ++i)
+        for (int64_t j = j0; j < j1; ++j) {
+            float out[2];
+            oracle_dot_ff_seq(Ah + i * lda, Al + i * lda, 1, Bh + j, Bl + j,
+                              ldb, K, out);
+            Ch[(i - i0) * ldc + (j - j0)] = out[0];
+            Cl[(i - i0) * ldc + (j - j0)] = out[1];
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact accumulation: a long fixed-point accumulator                       */
+/* ------------------------------------------------------------------------ */
+/*
+ * Every finite binary32 value is M * 2^E with M an integer, |M| < 2^24, and
+ * E >= -149; a product of two is M1*M2 * 2^(E1+E2), |M1*M2| < 2^48,
+ * E1+E2 >= -298.  The accumulator holds sum(value) / 2^LA_EMIN as an integer
+ * in base-2^32 limbs; each limb is a signed 64-bit word so that it can absorb
+ * 2^31 additions of 32-bit pieces before carries must be propagated.
+ */
+#define LA_LIMBS 24
+#define LA_EMIN (-384) /* weight of bit 0 of limb 0 */
+
+int oracle_exact_limbs(void) { return LA_LIMBS; }
+int oracle_exact_emin(void) { return LA_EMIN; }
+
+typedef struct {
+    int64_t limb[LA_LIMBS];
+    int64_t pending; /* additions since the last carry propagation */
+} long_acc;
+
+static void la_normalise(long_acc *acc)
+{
+    for (int i = 0; i < LA_LIMBS - 1; ++i) {
+        int64_t carry = acc->limb[i] >> 32; /* floor division by 2^32 */
+        acc->limb[i] -= carry * ((int64_t)1 << 32);
+        acc->limb[i + 1] += carry;
+    }
+    acc->pending = 0;
+}
+
+/* binary32 -> (M, E) with value = M * 2^E exactly (zero gives M = 0). */
+static void f32_decompose(float v, int64_t *m, int *e)
+{
+    if (v == 0.0f) {
+        *m = 0;
+        *e = 0;
+        return;
+    }
+    int ex;
+    float frac = frexpf(v, &ex); /* v = frac * 2^ex, 0.5 <= |frac| < 1 */
+    *m = (int64_t)ldexpf(frac, 24); /* exact: frac has at most 24 bits */
+    *e = ex - 24;
+}
+
+/* acc += m * 2^e, |m| < 2^62, e >= LA_EMIN. */
+static void la_add_scaled(long_acc *acc, int64_t m, int e)
+{
+    if (m == 0)
+        return;
+    int pos = e - LA_EMIN;
+    int neg = m < 0;
+    unsigned __int128 mag = (unsigned __int128)(neg ? -(uint64_t)m : (uint64_t)m);
+    mag <<= (pos % 32);
+    int li = pos / 32;
+    for (int k = 0; k < 4 && mag != 0; ++k) {
+        int64_t piece = (int64_t)(uint32_t)(mag & 0xffffffffu);
+        acc->limb[li + k] += neg ? -piece : piece;
+        mag >>= 32;
+    }
+    if (++acc->pending >= ((int64_t)1 << 30))
+        la_normalise(acc);
+}
+
+static void la_add_product(long_acc *acc, float a, float b)
+{
+    int64_t ma, mb;
+    int ea, eb;
+    f32_decompose(a, &ma, &ea);
+    f32_decompose(b, &mb, &eb);
+    la_add_scaled(acc, ma * mb, ea + eb);
+}
+
+static void la_store(long_acc *acc, int64_t *limbs_out)
+{
+    la_normalise(acc);
+    memcpy(limbs_out, acc->limb, sizeof(acc->limb));
+}
+
+/* Exact sum_i x_i*y_i (FP32 inputs, strided).  limbs_out[LA_LIMBS] receives
+ * the result as sum_k limbs_out[k] * 2^(32k + LA_EMIN); every limb but the
+ * last lies in [0, 2^32), the last carries the sign. */
+void oracle_exact_dot(const float *x, int64_t incx, const float *y,
+                      int64_t incy, int64_t n, int64_t *limbs_out)
+{
+    long_acc acc;
+    memset(&acc, 0, sizeof(acc));
+    for (int64_t i = 0; i < n; ++i)
+        la_add_product(&acc, x[i * incx], y[i * incy]);
+    la_store(&acc, limbs_out);
+}
+
+/* Exact sum_i (xh_i + xl_i) * (yh_i + yl_i) (float-float inputs, strided). */
+void oracle_exact_dot_ff(const float *xh, const float *xl, int64_t incx,
+                         const float *yh, const float *yl, int64_t incy,
+                         int64_t n, int64_t *limbs_out)
+{
+    long_acc acc;
+    memset(&acc, 0, sizeof(acc));
+    for (int64_t i = 0; i < n; ++i) {
+        float a = xh[i * incx], al = xl[i * incx];
+        float b = yh[i * incy], bl = yl[i * incy];
+        la_add_product(&acc, a, b);
+        la_add_product(&acc, a, bl);
+        la_add_product(&acc, al, b);
+        la_add_product(&acc, al, bl);
+    }
+    la_store(&acc, limbs_out);
+}
+
+/* Batched exact dots over concatenated FP32 vectors: vector v occupies
+ * [offsets[v], offsets[v+1]).  limbs_out has nvec * LA_LIMBS entries. */
+void oracle_exact_dot_batched(const float *x, const float *y,
+                              const int64_t *offsets, int64_t nvec,
+                              int64_t *limbs_out)
+{
+    for (int64_t v = 0; v < nvec; ++v)
+        oracle_exact_dot(x + offsets[v], 1, y + offsets[v], 1,
+                         offsets[v + 1] - offsets[v], limbs_out + v * LA_LIMBS);
+}
+
+/* Sequential float-float dots over concatenated FP32 vectors (the CPU
+ * baseline of the batched reduction): out2 has 2 * nvec entries. */
+void oracle_dot_seq_batched(const float *x, const float *y,
+                            const int64_t *offsets, int64_t nvec, float *out2)
+{
+    for (int64_t v = 0; v < nvec; ++v)
+        oracle_dot_seq(x + offsets[v], y + offsets[v],
+                       offsets[v + 1] - offsets[v], out2 + 2 * v);
+}
+
+/* Exact GEMM entries C_ij = sum_k (Ah+Al)_ik (Bh+Bl)_kj for a list of
+ * (i, j) pairs (row-major A and B). */
+void oracle_exact_gemm_entries(int64_t K, const float *Ah, const float *Al,
+                               int64_t lda, const float *Bh, const float *Bl,
+                               int64_t ldb, const int64_t *rows,
+                               const int64_t *cols, int64_t count,
+                               int64_t *limbs_out)
+{
+    for (int64_t t = 0; t < count; ++t) {
+        int64_t i = rows[t], j = cols[t];
+        oracle_exact_dot_ff(Ah + i * lda, Al + i * lda, 1, Bh + j, Bl + j, ldb,
+                            K, limbs_out + t * LA_LIMBS);
+    }
+}
+
+/* Exact |A| |B| entries: sum_k |(Ah+Al)_ik| |(Bh+Bl)_kj|, the normwise scale
+ * for GEMM errors.  |Ah + Al| is taken with the sign of Ah + Al, which for a
+ * float-float number is the sign of Ah (or of Al when Ah is zero). */
+void oracle_exact_absgemm_entries(int64_t K, const float *Ah, const float *Al,
+                                  int64_t lda, const float *Bh, const float *Bl,
+                                  int64_t ldb, const int64_t *rows,
+                                  const int64_t *cols, int64_t count,
+                                  int64_t *limbs_out)
+{
+    for (int64_t t = 0; t < count; ++t) {
+        int64_t i = rows[t], j = cols[t];
+        long_acc acc;
+        memset(&acc, 0, sizeof(acc));
+        for (int64_t k = 0; k < K; ++k) {
+            float a = Ah[i * lda + k], al = Al[i * lda + k];
+            float b = Bh[k * ldb + j], bl = Bl[k * ldb + j];
+            float sa = (a > 0.0f || (a == 0.0f && al > 0.0f)) ? 1.0f : -1.0f;
+            float sb = (b > 0.0f || (b == 0.0f && bl > 0.0f)) ? 1.0f : -1.0f;
+            a *= sa; al *= sa; b *= sb; bl *= sb;
+            la_add_product(&acc, a, b);
+            la_add_product(&acc, a, bl);
+            la_add_product(&acc, al, b);
+            la_add_product(&acc, al, bl);
+        }
+        la_store(&acc, limbs_out + t * LA_LIMBS);
+    }
+}

@@ -1,0 +1,92 @@
+"""The pins must reject a wrong oracle.
+
+Each case plants one plausible mistake (a dropped term, a wrong sign, index
+or constant, a transposed operand, the Mul22 typo as printed) in a copy of
+``oracle.c``, builds the copy with the same flags, and checks that at least
+one of the pins aimed at that part of the oracle fails on it.  Everything
+runs on the CPU; the real oracle is never modified.
+"""
+import os
+
+import pytest
+
+import oracle
+import test_oracle_operators as OPS
+import test_oracle_primitives as PRIM
+import test_oracle_reductions as RED
+
+_SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+
+PRIM_PINS = [
+    lambda: PRIM.test_add12_is_exact_and_rounds_like_ieee(-40, 40),
+    PRIM.test_add12_sterbenz_pairs_have_zero_error,
+    PRIM.test_split_exhaustive_unit_binade,
+    lambda: PRIM.test_mul12_is_exact(False, -50, 50),
+    lambda: PRIM.test_mul12_is_exact(True, -50, 50),
+]
+OP_PINS = [
+    OPS.test_add22_zero_low_words_is_the_exact_add12_pair,
+    OPS.test_add22_identities,
+    lambda: OPS.test_add22_error_bound("mixed", "add"),
+    lambda: OPS.test_add22_error_bound("near", "add"),
+    lambda: OPS.test_mul22_zero_low_words_is_the_exact_product_pair(False),
+    lambda: OPS.test_mul22_relative_error_bound("random", False),
+    OPS.test_div22_identities,
+    lambda: OPS.test_div22_relative_error_bound("random", False),
+]
+RED_PINS = [
+    lambda: RED.test_exact_dot_rounds_to_fsum(-20, 20),
+    RED.test_exact_dot_brute_force_and_extremes,
+    RED.test_dot_seq_single_term_is_the_exact_product_pair,
+    lambda: RED.test_dot_seq_error_bound(1000),
+    RED.test_gemm_identity_returns_a,
+    RED.test_gemm_block_and_exact_entries,
+]
+
+# (name, original text, planted text, pins expected to catch it)
+MUTATIONS = [
+    ("add12_error_sign", "float r = (a - (s - v)) + (b - v);",
+     "float r = (a - (s - v)) - (b - v);", PRIM_PINS),
+    ("add12_wrong_operand", "float v = s - a;", "float v = s - b;", PRIM_PINS),
+    ("split_constant", "const float c_split = 4097.0f;", "const float c_split = 4096.0f;",
+     PRIM_PINS),
+    ("split_low_word", "float a_lo = a - a_hi;", "float a_lo = a - a_big;", PRIM_PINS),
+    ("dekker_transposed_term", "float err2 = err1 - (al * bh);",
+     "float err2 = err1 - (ah * bl);", PRIM_PINS),
+    ("fma_sign", "*y_out = fmaf(a, b, -x);", "*y_out = fmaf(a, b, x);", PRIM_PINS),
+    ("add22_branch_flipped", "if (fabsf(ah) >= fabsf(bh))", "if (fabsf(ah) <= fabsf(bh))",
+     OP_PINS),
+    ("add22_dropped_low_word", "s = (((ah - r) + bh) + bl) + al;",
+     "s = (((ah - r) + bh) + bl);", OP_PINS),
+    ("mul22_printed_typo", "add12(t1, t3, rh, rl);", "add12(t1, t2, rh, rl);", OP_PINS),
+    ("mul22_wrong_index", "float t3 = ((ah * bl) + (al * bh)) + t2;",
+     "float t3 = ((ah * bl) + (al * bl)) + t2;", OP_PINS),
+    ("div22_sign", "float t = (((ah - u) - uu) + al) - (c * bl);",
+     "float t = (((ah - u) - uu) + al) + (c * bl);", OP_PINS),
+    ("div22_dropped_term", "float t = (((ah - u) - uu) + al) - (c * bl);",
+     "float t = ((ah - u) + al) - (c * bl);", OP_PINS),
+    ("exact_shift", "mag <<= (pos % 32);", "mag <<= (pos % 31);", RED_PINS),
+    ("exact_exponent", "*e = ex - 24;", "*e = ex - 23;", RED_PINS),
+    ("dot_dropped_error_term", "        add22(acc_h, acc_l, p, e, &acc_h, &acc_l);",
+     "        add22(acc_h, acc_l, p, 0.0f, &acc_h, &acc_l);", RED_PINS),
+    ("gemm_transposed_stride", "Bh + j, Bl + j,\n                              ldb, K, out);",
+     "Bh + j, Bl + j,\n                              1, K, out);", RED_PINS),
+]
+
+
+@pytest.mark.parametrize("name,orig,planted,pins", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_reject_planted_mistake(tmp_path, name, orig, planted, pins):
+    src = open(_SRC).read()
+    assert src.count(orig) == 1, f"mutation anchor for {name} not unique"
+    mutated = tmp_path / "oracle_mut.c"
+    mutated.write_text(src.replace(orig, planted))
+    so = oracle.build(force=True, src=str(mutated), out=str(tmp_path / "liboracle_mut.so"))
+    caught = []
+    with oracle.using_library(so):
+        for pin in pins:
+            try:
+                pin()
+            except (AssertionError, ValueError, ZeroDivisionError, OverflowError):
+                caught.append(pin)
+                break
+    assert caught, f"no pin rejects the planted mistake {name}"
