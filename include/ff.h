@@ -1,0 +1,135 @@
+/*
+ * ff.h -- C ABI of libff: float-float arithmetic on AMD Instinct MI355X (gfx950).
+ *
+ * A float-float number is the unevaluated sum hi + lo of two IEEE binary32
+ * words (Da Graca & Defour, "Implementation of float-float operators on
+ * graphics hardware", section 4: the double-double format carried over to
+ * single precision).  Arrays of float-float numbers are stored as two
+ * separate planes (structure of arrays): hi[0..n) and lo[0..n).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory    Every array pointer is a DEVICE pointer owned by the caller (for
+ *           example memory allocated by PyTorch on the current device).  The
+ *           library never allocates, frees or retains device memory; scratch
+ *           space, where needed, is a caller-provided workspace whose size is
+ *           returned by the matching *_workspace_size() function.
+ * Streams   `stream` is a hipStream_t passed as void*; NULL is the null
+ *           stream.  Work is enqueued asynchronously on that stream, on the
+ *           current HIP device, and is complete when the stream is.
+ * Checks    Arguments are validated on the host, synchronously, before any
+ *           HIP call: an invalid call returns an error status and enqueues
+ *           nothing.  A size of zero is a valid no-op returning FF_OK.
+ *           Floating-point data never cause an error: NaN and infinity
+ *           propagate as IEEE arithmetic makes them, and division by zero
+ *           gives IEEE infinities/NaN (not a meaningful float-float value).
+ * Alignment Float pointers must be 4-byte aligned (FF_ERR_ALIGN otherwise).
+ *           16-byte aligned planes take the vectorised fast path.
+ * Aliasing  An output plane may be the same array as an input plane (in-place
+ *           operation); partially overlapping arrays are undefined.
+ * Numerics  Device code is compiled with contraction off, binary32 denormals
+ *           preserved and correctly rounded binary32 division, so that each
+ *           operator performs exactly the operation sequence documented for
+ *           it; elementwise results are therefore reproducible bit for bit.
+ * Threads   Entry points hold no mutable global state and may be called from
+ *           several host threads.
+ */
+#ifndef FF_H
+#define FF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FF_ABI_VERSION 1
+
+typedef int32_t ff_status;
+
+#define FF_OK              0 /* success (work enqueued, or nothing to do)   */
+#define FF_ERR_NULL        1 /* a required pointer is NULL                  */
+#define FF_ERR_SIZE        2 /* negative or inconsistent size / dimension   */
+#define FF_ERR_ALIGN       3 /* pointer not aligned to its element type     */
+#define FF_ERR_WORKSPACE   4 /* workspace missing or smaller than required  */
+#define FF_ERR_UNSUPPORTED 5 /* device is not gfx950, or option unsupported */
+#define FF_ERR_HIP         6 /* the HIP runtime reported an error (launch)  */
+#define FF_ERR_ARG         7 /* invalid enumeration value or option         */
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *ff_status_str(ff_status status);
+
+/* FF_ABI_VERSION of the built library. */
+int32_t ff_abi_version(void);
+
+/* Static string describing how the library was built: target, contraction,
+ * denormal mode, division mode, TwoProd variants. */
+const char *ff_build_info(void);
+
+/* Text of the last HIP error seen by an entry point on the calling host
+ * thread ("" if none). */
+const char *ff_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Elementwise operators on n float-float pairs:                            */
+/*     (r_hi[i], r_lo[i]) = OP((a_hi[i], a_lo[i]), (b_hi[i], b_lo[i]))      */
+/* All ten planes hold n binary32 values.  Results are bit-identical to the */
+/* documented binary32 operation sequence.  Errors: FF_ERR_SIZE (n < 0),    */
+/* FF_ERR_NULL (a NULL plane, n > 0), FF_ERR_ALIGN, FF_ERR_HIP.             */
+/* ------------------------------------------------------------------------ */
+
+/* Add22 (section 4.1, Add22 theorem): r = ah (+) bh; if |ah| >= |bh| then
+ * s = (((ah (-) r) (+) bh) (+) bl) (+) al, else s = (((bh (-) r) (+) ah)
+ * (+) al) (+) bl; result Add12(r, s), with the branch-free six-operation
+ * Add12 (Add12 theorem).  |error| <= max(2^-24 |al + bl|, 2^-44 |a + b|). */
+ff_status ff_add(const float *a_hi, const float *a_lo, const float *b_hi,
+                 const float *b_lo, float *r_hi, float *r_lo, int64_t n,
+                 void *stream);
+
+/* Sub22: Add22 of a and -b (negating both words of b is exact). */
+ff_status ff_sub(const float *a_hi, const float *a_lo, const float *b_hi,
+                 const float *b_lo, float *r_hi, float *r_lo, int64_t n,
+                 void *stream);
+
+/* Mul22 (section 4.1, Mul22 theorem) with the exact product of the high
+ * words from one fused multiply-add, (t1, t2) = (ah*bh, fma(ah, bh, -t1));
+ * t3 = ((ah (x) bl) (+) (al (x) bh)) (+) t2; result Add12(t1, t3).
+ * (The paper prints Add12(t1, t2) as the last step, which leaves t3 unused;
+ * Add12(t1, t3) is the operator its theorem describes.)
+ * Relative error <= 2^-44. */
+ff_status ff_mul(const float *a_hi, const float *a_lo, const float *b_hi,
+                 const float *b_lo, float *r_hi, float *r_lo, int64_t n,
+                 void *stream);
+
+/* Mul22 with the high-word product computed by Dekker's Mul12 through Split
+ * with the constant 2^12 + 1 (section 4.1, Split and Mul12 theorems), as the
+ * paper does on hardware without a fused multiply-add.  Bit-identical to
+ * ff_mul whenever the product's error word is representable (no underflow). */
+ff_status ff_mul_dekker(const float *a_hi, const float *a_lo,
+                        const float *b_hi, const float *b_lo, float *r_hi,
+                        float *r_lo, int64_t n, void *stream);
+
+/* Div22 (not defined by the paper; Dekker's div2, the source the paper cites
+ * for Split and Mul12): c = ah (/) bh; (u, uu) = c*bh exactly (FMA);
+ * cc = ((((ah (-) u) (-) uu) (+) al) (-) (c (x) bl)) (/) bh;
+ * result Add12(c, cc).  (/) is correctly rounded binary32 division.
+ * Relative error <= 2^-44 (measured, see the test-suite). */
+ff_status ff_div(const float *a_hi, const float *a_lo, const float *b_hi,
+                 const float *b_lo, float *r_hi, float *r_lo, int64_t n,
+                 void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Measurement probe                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* dst[i] = src[i] for i < n (binary32), with the same load/store pattern as
+ * the elementwise operators: the HBM bandwidth reference for roofline and
+ * counter calibration.  Errors as for the elementwise operators. */
+ff_status ff_copy(const float *src, float *dst, int64_t n, void *stream);
+
+#ifdef __cplusplus
+} /* extern "C" */
+#endif
+
+#endif /* FF_H */

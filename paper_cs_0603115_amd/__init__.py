@@ -1,0 +1,122 @@
+"""Float-float (hi + lo binary32) arithmetic on AMD Instinct MI355X.
+
+A thin Python binding over the C ABI of ``libff.so`` (``include/ff.h``):
+every function here only checks and marshals arguments; every arithmetic
+step runs in the library's HIP kernels.  PyTorch provides device memory and
+streams.
+
+A float-float tensor is a float32 tensor of shape ``(2, *shape)`` whose
+plane 0 holds the high words and plane 1 the low words, each plane
+contiguous (structure of arrays).  Work is enqueued on the current torch
+stream unless ``stream`` is given.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import DotCfg, FFError, check, lib
+
+__all__ = [
+    "lib", "FFError", "DotCfg", "build_info",
+    "ff_add", "ff_sub", "ff_mul", "ff_mul_dekker", "ff_div", "ff_copy",
+    "ff_empty", "ff_zeros",
+]
+
+
+def build_info() -> str:
+    """How the loaded library was built (target, numerics flags)."""
+    return lib.ff_build_info().decode()
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _check_ff(t: torch.Tensor, name: str) -> None:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32:
+        raise TypeError(f"{name}: expected a float32 tensor")
+    if t.dim() < 1 or t.shape[0] != 2:
+        raise ValueError(f"{name}: a float-float tensor has shape (2, ...), got {tuple(t.shape)}")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be on a HIP device (libff runs on the GPU only)")
+    if not (t[0].is_contiguous() and t[1].is_contiguous()):
+        raise ValueError(f"{name}: each plane must be contiguous")
+
+
+def _planes(t: torch.Tensor):
+    return ctypes.c_void_p(t[0].data_ptr()), ctypes.c_void_p(t[1].data_ptr())
+
+
+def ff_empty(shape, device="cuda") -> torch.Tensor:
+    """Uninitialised float-float tensor of the given value shape."""
+    return torch.empty((2, *tuple(shape)), dtype=torch.float32, device=device)
+
+
+def ff_zeros(shape, device="cuda") -> torch.Tensor:
+    """Float-float zeros of the given value shape."""
+    return torch.zeros((2, *tuple(shape)), dtype=torch.float32, device=device)
+
+
+def _elementwise(name: str, a: torch.Tensor, b: torch.Tensor, out, stream) -> torch.Tensor:
+    _check_ff(a, "a")
+    _check_ff(b, "b")
+    if a.shape != b.shape:
+        raise ValueError(f"{name}: operand shapes differ: {tuple(a.shape)} vs {tuple(b.shape)}")
+    if a.device != b.device:
+        raise ValueError(f"{name}: operands on different devices")
+    if out is None:
+        out = torch.empty_like(a)
+    else:
+        _check_ff(out, "out")
+        if out.shape != a.shape:
+            raise ValueError(f"{name}: out has shape {tuple(out.shape)}")
+    n = a[0].numel()
+    ah, al = _planes(a)
+    bh, bl = _planes(b)
+    rh, rl = _planes(out)
+    with torch.cuda.device(a.device):
+        check(name, getattr(lib, name)(ah, al, bh, bl, rh, rl, n, _stream_handle(stream)))
+    return out
+
+
+def ff_add(a, b, out=None, stream=None):
+    """Float-float sum a + b (Add22, section 4.1)."""
+    return _elementwise("ff_add", a, b, out, stream)
+
+
+def ff_sub(a, b, out=None, stream=None):
+    """Float-float difference a - b (Add22 of a and -b)."""
+    return _elementwise("ff_sub", a, b, out, stream)
+
+
+def ff_mul(a, b, out=None, stream=None):
+    """Float-float product a * b (Mul22, FMA TwoProd)."""
+    return _elementwise("ff_mul", a, b, out, stream)
+
+
+def ff_mul_dekker(a, b, out=None, stream=None):
+    """Float-float product a * b (Mul22 with Dekker's Split-based Mul12)."""
+    return _elementwise("ff_mul_dekker", a, b, out, stream)
+
+
+def ff_div(a, b, out=None, stream=None):
+    """Float-float quotient a / b (Div22, Dekker's div2)."""
+    return _elementwise("ff_div", a, b, out, stream)
+
+
+def ff_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> torch.Tensor:
+    """dst <- src for float32 tensors (the bandwidth probe kernel)."""
+    if src.dtype != torch.float32 or dst.dtype != torch.float32:
+        raise TypeError("ff_copy: float32 tensors expected")
+    if not (src.is_contiguous() and dst.is_contiguous()) or src.numel() != dst.numel():
+        raise ValueError("ff_copy: contiguous tensors of equal size expected")
+    if not src.is_cuda:
+        raise ValueError("ff_copy: tensors must be on a HIP device")
+    with torch.cuda.device(src.device):
+        check("ff_copy", lib.ff_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                     src.numel(), _stream_handle(stream)))
+    return dst

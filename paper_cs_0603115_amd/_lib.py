@@ -1,0 +1,84 @@
+"""ctypes loader for ``libff.so`` (the C ABI declared in ``include/ff.h``).
+
+The library is built in-tree by ``paper_cs_0603115_amd.build``.  There is no
+fallback: if the library is missing or stale the import of this module fails
+with an error that says how to build it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libff.so")
+
+_P = ctypes.c_void_p          # device pointers and streams
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_sz = ctypes.c_size_t
+_st = ctypes.c_int32          # ff_status
+
+
+class DotCfg(ctypes.Structure):
+    """``ff_dot_cfg``: launch shape of the batched float-float dot."""
+    _fields_ = [("block", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("unroll", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.block, self.chunk, self.grid, self.unroll)
+
+
+_EW = ([_P, _P, _P, _P, _P, _P, _i64, _P], _st)
+
+# name -> (argtypes, restype); must list every function of include/ff.h.
+SIGNATURES = {
+    "ff_status_str": ([_st], ctypes.c_char_p),
+    "ff_abi_version": ([], _i32),
+    "ff_build_info": ([], ctypes.c_char_p),
+    "ff_last_error": ([], ctypes.c_char_p),
+    "ff_add": _EW,
+    "ff_sub": _EW,
+    "ff_mul": _EW,
+    "ff_mul_dekker": _EW,
+    "ff_div": _EW,
+    "ff_copy": ([_P, _P, _i64, _P], _st),
+}
+
+FF_OK = 0
+STATUS_NAMES = {0: "FF_OK", 1: "FF_ERR_NULL", 2: "FF_ERR_SIZE", 3: "FF_ERR_ALIGN",
+                4: "FF_ERR_WORKSPACE", 5: "FF_ERR_UNSUPPORTED", 6: "FF_ERR_HIP",
+                7: "FF_ERR_ARG"}
+
+
+class FFError(RuntimeError):
+    """A libff entry point returned a status other than FF_OK."""
+
+    def __init__(self, fn: str, status: int, detail: str = ""):
+        self.status = status
+        name = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{fn} failed: {name}" + (f" ({detail})" if detail else ""))
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"libff.so not found at {LIB_PATH}: build the HIP library first "
+            "(python -m paper_cs_0603115_amd.build, or __graft_entry__.build())")
+    handle = ctypes.CDLL(LIB_PATH)
+    for name, (args, res) in SIGNATURES.items():
+        fn = getattr(handle, name)
+        fn.argtypes = args
+        fn.restype = res
+    if handle.ff_abi_version() != 1:
+        raise ImportError("libff.so ABI version mismatch: rebuild the library")
+    return handle
+
+
+lib = _load()
+
+
+def check(fn_name: str, status: int) -> None:
+    """Raise FFError unless ``status`` is FF_OK."""
+    if status != FF_OK:
+        detail = lib.ff_last_error().decode() if status == 6 else ""
+        raise FFError(fn_name, status, detail)

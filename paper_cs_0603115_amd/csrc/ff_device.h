@@ -1,0 +1,120 @@
+// ff_device.h -- float-float device primitives for gfx950.
+//
+// Each function performs the binary32 operation sequence of its operator,
+// nothing more: the translation unit is compiled with -ffp-contract=off
+// (and the pragma below), IEEE binary32 denormals and correctly rounded
+// division, so every (+), (-), (x), (/) is one rounded VALU instruction.
+// The only fused operation is the explicit __builtin_fmaf of TwoProd.
+//
+// Paper references are to Da Graca & Defour, "Implementation of float-float
+// operators on graphics hardware", section 4.1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#pragma clang fp contract(off)
+
+namespace ffd {
+
+// Add12 theorem (Knuth): s = a (+) b, r = (a + b) - s exactly; the
+// branch-free six-operation form.
+__device__ __forceinline__ void add12(float a, float b, float &s, float &r)
+{
+    s = a + b;
+    const float v = s - a;
+    r = (a - (s - v)) + (b - v);
+}
+
+// Split theorem (Dekker) with p = 24, s = 12: a = hi + lo, 12 + 12 bits.
+__device__ __forceinline__ void split(float a, float &hi, float &lo)
+{
+    const float c = 4097.0f * a;
+    const float big = c - a;
+    hi = c - big;
+    lo = a - hi;
+}
+
+// Mul12 theorem (Dekker): x = a (x) b and y = a*b - x via Split.
+__device__ __forceinline__ void mul12_dekker(float a, float b, float &x, float &y)
+{
+    x = a * b;
+    float ah, al, bh, bl;
+    split(a, ah, al);
+    split(b, bh, bl);
+    const float e1 = x - (ah * bh);
+    const float e2 = e1 - (al * bh);
+    const float e3 = e2 - (ah * bl);
+    y = (al * bl) - e3;
+}
+
+// TwoProd with one fused multiply-add (v_fma_f32): the same pair as Mul12
+// whenever the error word is representable.
+__device__ __forceinline__ void mul12_fma(float a, float b, float &x, float &y)
+{
+    x = a * b;
+    y = __builtin_fmaf(a, b, -x);
+}
+
+// Add22 theorem.  The paper's branch on |ah| >= |bh| is taken as a select
+// of which operand plays "a": both arms then evaluate the same chain
+// (((x_h (-) r) (+) y_h) (+) y_l) (+) x_l, which is the printed expression
+// of the arm selected, so the bits are those of the branching form.
+__device__ __forceinline__ void add22(float ah, float al, float bh, float bl,
+                                      float &rh, float &rl)
+{
+    const float r = ah + bh;
+    const bool a_big = __builtin_fabsf(ah) >= __builtin_fabsf(bh);
+    const float xh = a_big ? ah : bh;
+    const float xl = a_big ? al : bl;
+    const float yh = a_big ? bh : ah;
+    const float yl = a_big ? bl : al;
+    const float s = (((xh - r) + yh) + yl) + xl;
+    add12(r, s, rh, rl);
+}
+
+// Mul22 theorem with final step Add12(t1, t3).
+template <bool DEKKER>
+__device__ __forceinline__ void mul22(float ah, float al, float bh, float bl,
+                                      float &rh, float &rl)
+{
+    float t1, t2;
+    if (DEKKER)
+        mul12_dekker(ah, bh, t1, t2);
+    else
+        mul12_fma(ah, bh, t1, t2);
+    const float t3 = ((ah * bl) + (al * bh)) + t2;
+    add12(t1, t3, rh, rl);
+}
+
+// Div22 after Dekker's div2 (the paper has no division).
+__device__ __forceinline__ void div22(float ah, float al, float bh, float bl,
+                                      float &rh, float &rl)
+{
+    const float c = ah / bh;
+    float u, uu;
+    mul12_fma(c, bh, u, uu);
+    const float t = (((ah - u) - uu) + al) - (c * bl);
+    const float cc = t / bh;
+    add12(c, cc, rh, rl);
+}
+
+// Operator codes shared by the elementwise kernels and the C ABI.
+enum Op : int { OP_ADD = 0, OP_SUB = 1, OP_MUL = 2, OP_MUL_DEKKER = 3, OP_DIV = 4 };
+
+template <int OP>
+__device__ __forceinline__ void apply(float ah, float al, float bh, float bl,
+                                      float &rh, float &rl)
+{
+    if constexpr (OP == OP_ADD)
+        add22(ah, al, bh, bl, rh, rl);
+    else if constexpr (OP == OP_SUB)
+        add22(ah, al, -bh, -bl, rh, rl);
+    else if constexpr (OP == OP_MUL)
+        mul22<false>(ah, al, bh, bl, rh, rl);
+    else if constexpr (OP == OP_MUL_DEKKER)
+        mul22<true>(ah, al, bh, bl, rh, rl);
+    else
+        div22(ah, al, bh, bl, rh, rl);
+}
+
+} // namespace ffd

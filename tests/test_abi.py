@@ -1,0 +1,114 @@
+"""The C ABI (include/ff.h) on the host: the library loads, exports every
+declared entry point, and rejects invalid arguments before any HIP call.
+
+No test here launches work: the validation paths return before touching the
+HIP runtime, so fake host addresses are safe.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_cs_0603115_amd as ff
+from paper_cs_0603115_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER_DIR = os.path.join(ROOT, "include")
+
+ERR_NULL, ERR_SIZE, ERR_ALIGN, ERR_WS, ERR_UNSUP, ERR_HIP, ERR_ARG = 1, 2, 3, 4, 5, 6, 7
+
+
+def declared_functions():
+    names = []
+    for fname in sorted(os.listdir(HEADER_DIR)):
+        if not fname.endswith(".h"):
+            continue
+        text = open(os.path.join(HEADER_DIR, fname)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        text = "\n".join(l for l in text.splitlines() if not l.lstrip().startswith("#"))
+        names += re.findall(r"\b(ff_\w+)\s*\([^;{]*\)\s*;", text)
+    return names
+
+
+def exported_symbols():
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    return {line.split()[-1] for line in out.splitlines() if line.strip()}
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    assert len(names) == len(set(names))
+    for required in ("ff_add", "ff_sub", "ff_mul", "ff_mul_dekker", "ff_div"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    exported = exported_symbols()
+    for name in declared_functions():
+        assert name in exported, f"{name} declared in include/ but not exported"
+        assert name in _lib.SIGNATURES, f"{name} missing from the Python binding"
+        assert hasattr(_lib.lib, name)
+    for name in _lib.SIGNATURES:
+        assert name in declared_functions(), f"{name} bound but not declared"
+
+
+def test_version_and_build_info():
+    assert ff.lib.ff_abi_version() == 1
+    info = ff.build_info()
+    for token in ("gfx950", "fp-contract=off", "f32-denormals=preserve",
+                  "f32-division=correctly-rounded"):
+        assert token in info
+
+
+def test_status_strings():
+    for code, name in _lib.STATUS_NAMES.items():
+        assert ff.lib.ff_status_str(code).decode() == name
+    assert ff.lib.ff_status_str(99).decode() == "FF_ERR_UNKNOWN"
+    assert ff.lib.ff_last_error().decode() == ""
+
+
+EW = ["ff_add", "ff_sub", "ff_mul", "ff_mul_dekker", "ff_div"]
+
+
+@pytest.mark.parametrize("name", EW)
+def test_elementwise_validation(name):
+    fn = getattr(ff.lib, name)
+    p = [4096 * (k + 1) for k in range(6)]          # fake 16-byte aligned addresses
+    assert fn(*p, -1, None) == ERR_SIZE
+    assert fn(*p, 0, None) == 0                     # no-op, nothing enqueued
+    assert fn(None, None, None, None, None, None, 0, None) == 0
+    for k in range(6):
+        q = list(p)
+        q[k] = None
+        assert fn(*q, 10, None) == ERR_NULL
+        q = list(p)
+        q[k] = p[k] + 2                             # not 4-byte aligned
+        assert fn(*q, 10, None) == ERR_ALIGN
+
+
+def test_copy_validation():
+    assert ff.lib.ff_copy(4096, 8192, -3, None) == ERR_SIZE
+    assert ff.lib.ff_copy(4096, 8192, 0, None) == 0
+    assert ff.lib.ff_copy(None, 8192, 4, None) == ERR_NULL
+    assert ff.lib.ff_copy(4097, 8192, 4, None) == ERR_ALIGN
+
+
+def test_python_binding_rejects_bad_tensors():
+    import torch
+    a = torch.zeros(2, 8)
+    with pytest.raises(ValueError):
+        ff.ff_add(a, a)                              # CPU tensor: the library is GPU-only
+    with pytest.raises(ValueError):
+        ff.ff_add(torch.zeros(3, 8), torch.zeros(3, 8))
+    with pytest.raises(TypeError):
+        ff.ff_add(a.double(), a.double())
+
+
+def test_ff_error_carries_status():
+    with pytest.raises(ff.FFError) as err:
+        _lib.check("ff_add", ERR_ALIGN)
+    assert err.value.status == ERR_ALIGN and "FF_ERR_ALIGN" in str(err.value)
