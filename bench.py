@@ -131,6 +131,19 @@ def main(argv=None) -> int:
     ms_per_step = elapsed * 1e3 / args.steps
 
     kernel_ms = {op: sum(s.elapsed_time(e) for s, e in events[op]) / args.steps for op in OPS}
+
+    # Bandwidth reference: the ff_copy probe (one plane in, one out, same
+    # 16-byte non-temporal pattern) over N binary32 words, after the timed
+    # region.  It also calibrates the HBM byte counters.
+    copy_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+    for s_ev, e_ev in copy_ev:
+        s_ev.record(stream)
+        ff.ff_copy(a[0], r[0], stream=stream)
+        e_ev.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = sum(s.elapsed_time(e) for s, e in copy_ev) / args.steps
+    copy_gbs = 8 * n / (copy_ms * 1e-3) / 1e9
     per_op = {op: {"ms": round(kernel_ms[op], 5),
                    "GB/s": round(BYTES_PER_FF_OP * n / (kernel_ms[op] * 1e-3) / 1e9, 1)}
               for op in OPS}
@@ -163,6 +176,8 @@ def main(argv=None) -> int:
             "traffic": None,
         },
         "per_op": per_op,
+        "copy_probe": {"ms": round(copy_ms, 5), "GB/s": round(copy_gbs, 1),
+                       "bytes": 8 * n, "dominant_frac_of_copy": round(achieved / copy_gbs, 4)},
     }
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle) on a bounded sample")

@@ -28,7 +28,7 @@ import torch
 
 __all__ = [
     "split_f64", "base_ff", "mixed_ff_pair", "batched_dot", "gaussian_ff",
-    "gaussian_f32", "join_f64", "random_f32", "random_ff",
+    "gaussian_f32", "join_f64", "random_f32", "random_ff", "scaled_normal",
 ]
 
 
@@ -138,6 +138,12 @@ def _scaled_normal(n: int, g: torch.Generator, device) -> torch.Tensor:
     # the scaling is exact whatever the device's exp2/pow accuracy.
     scale = ((k + 127) << 23).view(torch.float32)
     return z * scale
+
+
+def scaled_normal(n: int, seed: int, device="cpu") -> torch.Tensor:
+    """n binary32 entries normal(0,1) * 2^k, k uniform integer in [-10, 10]
+    (the entry distribution of the batched dot workload)."""
+    return _scaled_normal(n, _gen(seed, device), device)
 
 
 def gaussian_ff(shape, seed: int, device="cpu") -> torch.Tensor:

@@ -120,6 +120,72 @@ ff_status ff_div(const float *a_hi, const float *a_lo, const float *b_hi,
                  void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Batched float-float dot products (reductions)                            */
+/* ------------------------------------------------------------------------ */
+/*
+ * nvec independent dot products over concatenated vectors: vector v owns the
+ * elements [offsets[v], offsets[v+1]) of x and y.  Every term is formed
+ * exactly -- TwoProd(x_i, y_i) for binary32 inputs, Mul22 for float-float
+ * inputs -- and accumulated with Add22 (section 4.1) in float-float.  The
+ * paper defines no reduction; compensated summation is its stated future
+ * work (section 7).
+ *
+ * Execution: one small planning launch (chunk table, counters) and ONE
+ * persistent launch that walks all chunks of all vectors.  Each chunk of
+ * `cfg->chunk` elements is reduced by one workgroup (per-lane float-float
+ * accumulators, a wavefront butterfly of Add22 over lane shuffles, then the
+ * wavefronts' partials in order through LDS) into a float-float partial;
+ * the workgroup that completes a vector's last chunk combines that vector's
+ * partials with an Add22 tree of fixed shape.  No floating-point atomics are
+ * used: for a given cfg the result is bitwise reproducible run to run.
+ * Different cfg values may give different (equally valid) last bits.
+ *
+ * Accuracy: |result - exact| is bounded by (tree depth) * 2^-44 * sum|x_i y_i|
+ * in the worst case; on random data it is far smaller (see the test-suite).
+ */
+
+/* Launch shape of the batched dot.  All-zero fields select the defaults. */
+typedef struct ff_dot_cfg {
+    int32_t block;  /* threads per workgroup: 256 or 512 (0: 256)           */
+    int32_t chunk;  /* elements per chunk, a multiple of 4, >= 64 (0: 16384) */
+    int32_t grid;   /* persistent workgroups; 0: 8 per compute unit          */
+    int32_t unroll; /* float4 groups loaded per lane per step: 1, 2 or 4     */
+} ff_dot_cfg;
+
+/* Bytes of device workspace ff_dot_batched / ff_dot_ff_batched need for
+ * nvec vectors holding total_len elements in all (cfg NULL: defaults).
+ * Returns 0 for invalid arguments. */
+size_t ff_dot_batched_workspace_size(int64_t total_len, int32_t nvec,
+                                     const ff_dot_cfg *cfg);
+
+/* out[v] = sum over [offsets[v], offsets[v+1]) of x_i * y_i, binary32
+ * inputs, float-float result (out_hi[v], out_lo[v]).
+ *   x, y       device, total_len binary32 each (16-byte aligned: fast path)
+ *   offsets    device, nvec + 1 int64, non-decreasing, offsets[0] >= 0,
+ *              offsets[nvec] <= total_len (violations give unspecified
+ *              results but never access memory outside the arrays)
+ *   cfg        host pointer or NULL (defaults)
+ *   ws         device workspace of ws_bytes >= the size queried above;
+ *              it must not be shared by launches that may overlap
+ *   out_hi/lo  device, nvec binary32 each; an empty vector gives (0, 0)
+ * Errors: FF_ERR_SIZE (nvec < 0, total_len < 0), FF_ERR_NULL, FF_ERR_ALIGN,
+ * FF_ERR_ARG (invalid cfg), FF_ERR_WORKSPACE, FF_ERR_HIP. */
+ff_status ff_dot_batched(const float *x, const float *y,
+                         const int64_t *offsets, int32_t nvec,
+                         int64_t total_len, const ff_dot_cfg *cfg, void *ws,
+                         size_t ws_bytes, float *out_hi, float *out_lo,
+                         void *stream);
+
+/* As ff_dot_batched for float-float inputs: the terms are Mul22 products
+ * (FMA TwoProd) of (x_hi, x_lo) and (y_hi, y_lo). */
+ff_status ff_dot_ff_batched(const float *x_hi, const float *x_lo,
+                            const float *y_hi, const float *y_lo,
+                            const int64_t *offsets, int32_t nvec,
+                            int64_t total_len, const ff_dot_cfg *cfg, void *ws,
+                            size_t ws_bytes, float *out_hi, float *out_lo,
+                            void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Measurement probe                                                        */
 /* ------------------------------------------------------------------------ */
 

@@ -21,6 +21,7 @@ from ._lib import DotCfg, FFError, check, lib
 __all__ = [
     "lib", "FFError", "DotCfg", "build_info",
     "ff_add", "ff_sub", "ff_mul", "ff_mul_dekker", "ff_div", "ff_copy",
+    "ff_dot_batched", "ff_dot_ff_batched", "ff_dot_batched_workspace_size",
     "ff_empty", "ff_zeros",
 ]
 
@@ -120,3 +121,83 @@ def ff_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> torch.Tensor:
         check("ff_copy", lib.ff_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
                                      src.numel(), _stream_handle(stream)))
     return dst
+
+
+# ------------------------------------------------------------------ reductions
+
+def _cfg_ptr(cfg):
+    if cfg is None:
+        return None
+    if isinstance(cfg, DotCfg):
+        return ctypes.byref(cfg)
+    return ctypes.byref(DotCfg(*cfg))
+
+
+def ff_dot_batched_workspace_size(total_len: int, nvec: int, cfg=None) -> int:
+    """Workspace bytes for a batched dot over ``nvec`` vectors of ``total_len``
+    elements in all."""
+    return int(lib.ff_dot_batched_workspace_size(int(total_len), int(nvec), _cfg_ptr(cfg)))
+
+
+def _check_offsets(offsets: torch.Tensor, device) -> int:
+    if offsets.dtype != torch.int64 or offsets.dim() != 1 or not offsets.is_contiguous():
+        raise ValueError("offsets: contiguous int64 vector of nvec + 1 entries expected")
+    if offsets.device != device:
+        raise ValueError("offsets must be on the same device as the data")
+    return offsets.numel() - 1
+
+
+def _workspace(nbytes: int, device, workspace):
+    if workspace is None:
+        return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+    if workspace.device != device or workspace.numel() * workspace.element_size() < nbytes:
+        raise ValueError("workspace too small or on another device")
+    return workspace
+
+
+def ff_dot_batched(x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, cfg=None,
+                   out=None, workspace=None, stream=None) -> torch.Tensor:
+    """Float-float dots of binary32 vectors: out[:, v] = sum of x*y over
+    [offsets[v], offsets[v+1]) (TwoProd terms, Add22 accumulation).
+    Returns a float-float tensor of shape (2, nvec)."""
+    for t, name in ((x, "x"), (y, "y")):
+        if t.dtype != torch.float32 or t.dim() != 1 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError(f"{name}: contiguous float32 vector on a HIP device expected")
+    if x.numel() != y.numel():
+        raise ValueError("x and y differ in length")
+    nvec = _check_offsets(offsets, x.device)
+    out = ff_empty((nvec,), device=x.device) if out is None else out
+    _check_ff(out, "out")
+    nbytes = ff_dot_batched_workspace_size(x.numel(), nvec, cfg)
+    ws = _workspace(nbytes, x.device, workspace)
+    oh, ol = _planes(out)
+    with torch.cuda.device(x.device):
+        check("ff_dot_batched", lib.ff_dot_batched(
+            ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+            ctypes.c_void_p(offsets.data_ptr()), nvec, x.numel(), _cfg_ptr(cfg),
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), oh, ol, _stream_handle(stream)))
+    return out
+
+
+def ff_dot_ff_batched(x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, cfg=None,
+                      out=None, workspace=None, stream=None) -> torch.Tensor:
+    """Float-float dots of float-float vectors (Mul22 terms, Add22
+    accumulation); x and y have shape (2, total).  Returns (2, nvec)."""
+    _check_ff(x, "x")
+    _check_ff(y, "y")
+    if x.shape != y.shape or x.dim() != 2:
+        raise ValueError("x and y must both have shape (2, total)")
+    nvec = _check_offsets(offsets, x.device)
+    out = ff_empty((nvec,), device=x.device) if out is None else out
+    _check_ff(out, "out")
+    total = x.shape[1]
+    nbytes = ff_dot_batched_workspace_size(total, nvec, cfg)
+    ws = _workspace(nbytes, x.device, workspace)
+    xh, xl = _planes(x)
+    yh, yl = _planes(y)
+    oh, ol = _planes(out)
+    with torch.cuda.device(x.device):
+        check("ff_dot_ff_batched", lib.ff_dot_ff_batched(
+            xh, xl, yh, yl, ctypes.c_void_p(offsets.data_ptr()), nvec, total, _cfg_ptr(cfg),
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), oh, ol, _stream_handle(stream)))
+    return out

@@ -98,6 +98,21 @@ __device__ __forceinline__ void div22(float ah, float al, float bh, float bl,
     add12(c, cc, rh, rl);
 }
 
+// Butterfly all-reduce of a float-float value over the 64 lanes of a
+// wavefront: at distance m = 32, 16, ..., 1 every lane adds its partner's
+// value with Add22.  Add22 is commutative bit for bit (swapping the operands
+// swaps which one the select calls "a" and leaves the chain unchanged), so
+// partners compute identical sums and every lane ends with the same bits.
+__device__ __forceinline__ void wave_allreduce_add22(float &h, float &l)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const float oh = __shfl_xor(h, m, 64);
+        const float ol = __shfl_xor(l, m, 64);
+        add22(h, l, oh, ol, h, l);
+    }
+}
+
 // Operator codes shared by the elementwise kernels and the C ABI.
 enum Op : int { OP_ADD = 0, OP_SUB = 1, OP_MUL = 2, OP_MUL_DEKKER = 3, OP_DIV = 4 };
 

@@ -112,3 +112,48 @@ def test_ff_error_carries_status():
     with pytest.raises(ff.FFError) as err:
         _lib.check("ff_add", ERR_ALIGN)
     assert err.value.status == ERR_ALIGN and "FF_ERR_ALIGN" in str(err.value)
+
+
+def test_dot_workspace_size():
+    size = ff.ff_dot_batched_workspace_size
+    assert size(0, 0) > 0 or size(0, 0) == 0
+    assert size(1 << 20, 10) > 0
+    assert size(-1, 10) == 0 and size(10, -1) == 0
+    assert size(100, 3, (0, 0, 0, 3)) == 0          # unroll must be 1, 2 or 4
+    assert size(100, 3, (0, 60, 0, 0)) == 0         # chunk >= 64
+    assert size(100, 3, (0, 66, 0, 0)) == 0         # chunk multiple of 4
+    assert size(100, 3, (128, 0, 0, 0)) == 0        # block 256 or 512
+    # grows with the chunk count (total / chunk + nvec partials)
+    assert size(1 << 24, 4, (256, 64, 0, 1)) > size(1 << 24, 4, (256, 16384, 0, 1))
+
+
+@pytest.mark.parametrize("name", ["ff_dot_batched", "ff_dot_ff_batched"])
+def test_dot_validation(name):
+    fn = getattr(ff.lib, name)
+    nplanes = 2 if name == "ff_dot_batched" else 4
+    planes = [4096 * (k + 1) for k in range(nplanes)]
+    offs, oh, ol, ws = 1 << 20, 2 << 20, 3 << 20, 4 << 20
+    need = ff.ff_dot_batched_workspace_size(1000, 8)
+
+    def call(planes=planes, offs=offs, nvec=8, total=1000, cfg=None, ws=ws, ws_bytes=need,
+             oh=oh, ol=ol):
+        cfgp = None if cfg is None else ctypes.byref(_lib.DotCfg(*cfg))
+        return fn(*planes, offs, nvec, total, cfgp, ws, ws_bytes, oh, ol, None)
+
+    assert call(nvec=-1) == ERR_SIZE
+    assert call(total=-5) == ERR_SIZE
+    assert call(nvec=0) == 0                           # nothing to do
+    assert call(cfg=(0, 0, 0, 3)) == ERR_ARG
+    assert call(cfg=(1024, 0, 0, 0)) == ERR_ARG
+    assert call(ws_bytes=need - 1) == ERR_WS
+    assert call(ws=None) == ERR_NULL
+    assert call(offs=None) == ERR_NULL
+    assert call(oh=None) == ERR_NULL
+    p = list(planes)
+    p[0] = None
+    assert call(planes=p) == ERR_NULL
+    p = list(planes)
+    p[-1] = planes[-1] + 1
+    assert call(planes=p) == ERR_ALIGN
+    assert call(offs=offs + 4) == ERR_ALIGN
+    assert call(ws=ws + 64) == ERR_ALIGN
