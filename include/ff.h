@@ -185,6 +185,90 @@ ff_status ff_dot_ff_batched(const float *x_hi, const float *x_lo,
                             size_t ws_bytes, float *out_hi, float *out_lo,
                             void *stream);
 
+/* Batched float-float sums: out[v] = sum over [offsets[v], offsets[v+1]) of
+ * x_i (binary32 terms (x_i, 0)), accumulated with Add22 exactly as the
+ * dots.  Arguments and errors as for ff_dot_batched. */
+ff_status ff_sum_batched(const float *x, const int64_t *offsets, int32_t nvec,
+                         int64_t total_len, const ff_dot_cfg *cfg, void *ws,
+                         size_t ws_bytes, float *out_hi, float *out_lo,
+                         void *stream);
+
+/* As ff_sum_batched for float-float terms (x_hi[i], x_lo[i]). */
+ff_status ff_sum_ff_batched(const float *x_hi, const float *x_lo,
+                            const int64_t *offsets, int32_t nvec,
+                            int64_t total_len, const ff_dot_cfg *cfg, void *ws,
+                            size_t ws_bytes, float *out_hi, float *out_lo,
+                            void *stream);
+
+/* Launch-shape autotuner for ff_dot_batched on this batch: times every
+ * candidate (block 256/512 x unroll 1/2/4 x chunk 4096..65536 x 2..16
+ * workgroups per compute unit) whose workspace fits in ws_bytes, `reps`
+ * launches each after one untimed launch, with HIP events on `stream`, and
+ * returns the fastest in *best with its mean time in *best_ms.  SYNCHRONOUS:
+ * waits for each candidate.  out_hi/out_lo receive the last candidate's
+ * result.  Errors: those of ff_dot_batched, FF_ERR_NULL (best/best_ms),
+ * FF_ERR_ARG (reps < 1), FF_ERR_WORKSPACE (no candidate fits). */
+ff_status ff_dot_batched_autotune(const float *x, const float *y,
+                                  const int64_t *offsets, int32_t nvec,
+                                  int64_t total_len, void *ws, size_t ws_bytes,
+                                  float *out_hi, float *out_lo, int32_t reps,
+                                  void *stream, ff_dot_cfg *best,
+                                  float *best_ms);
+
+/* ------------------------------------------------------------------------ */
+/* Matrix-vector product and its backward pass (differentiation)            */
+/* ------------------------------------------------------------------------ */
+/*
+ * A is an M x N float-float matrix, row-major, two planes with leading
+ * dimension lda >= N (elements); vectors are float-float planes.  Every term
+ * is a Mul22 product (FMA TwoProd) and sums use Add22 (section 4.1).
+ *
+ * algo FF_MATVEC_FAST  -- tiled kernels: one workgroup per row (forward);
+ *                         one fused pass over A writing dA and per-band
+ *                         partial column sums of A^T g (backward), combined
+ *                         in band order by a second small launch.
+ * algo FF_MATVEC_PLAIN -- the plain float-float loops: one thread per row
+ *                         (forward) or per column (backward), sums in index
+ *                         order, a separate launch for dA.  Bit-identical to
+ *                         the sequential definition.
+ */
+#define FF_MATVEC_FAST  0
+#define FF_MATVEC_PLAIN 1
+
+/* y = A x.  y_hi/y_lo: M values each.  Errors: FF_ERR_SIZE (M, N < 0 or
+ * lda < N), FF_ERR_NULL, FF_ERR_ALIGN, FF_ERR_ARG (algo), FF_ERR_HIP. */
+ff_status ff_matvec(int64_t M, int64_t N, const float *A_hi, const float *A_lo,
+                    int64_t lda, const float *x_hi, const float *x_lo,
+                    float *y_hi, float *y_lo, int32_t algo, void *stream);
+
+/* Workspace bytes of ff_matvec_backward (partial column sums of the fast
+ * algorithm; 0 for the plain one). */
+size_t ff_matvec_backward_workspace_size(int64_t M, int64_t N, int32_t algo);
+
+/* Backward pass of y = A x for an upstream gradient g = dL/dy (M values):
+ *   dA = g x^T      dA_ij = Mul22(g_i, x_j), bit-identical to Mul22
+ *   dx = A^T g      dx_j  = sum_i Mul22(g_i, A_ij) with Add22
+ * dA (leading dimension ldda >= N) may be NULL to skip it; dx may be NULL to
+ * skip it.  The fast algorithm reads A once and writes dA once in the same
+ * pass.  Errors as ff_matvec, plus FF_ERR_WORKSPACE. */
+ff_status ff_matvec_backward(int64_t M, int64_t N, const float *A_hi,
+                             const float *A_lo, int64_t lda, const float *x_hi,
+                             const float *x_lo, const float *g_hi,
+                             const float *g_lo, float *dA_hi, float *dA_lo,
+                             int64_t ldda, float *dx_hi, float *dx_lo,
+                             int32_t algo, void *ws, size_t ws_bytes,
+                             void *stream);
+
+/* Backward pass of the float-float dot s = sum_i x_i y_i for an upstream
+ * gradient g = dL/ds (ONE float-float value, device pointers g_hi, g_lo):
+ *   dx_i = Mul22(g, y_i),  dy_i = Mul22(g, x_i)   (elementwise, n values).
+ * Either output pair may be NULL to skip it. */
+ff_status ff_dot_backward(const float *g_hi, const float *g_lo,
+                          const float *x_hi, const float *x_lo,
+                          const float *y_hi, const float *y_lo, float *dx_hi,
+                          float *dx_lo, float *dy_hi, float *dy_lo, int64_t n,
+                          void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Measurement probe                                                        */
 /* ------------------------------------------------------------------------ */

@@ -16,12 +16,14 @@ import ctypes
 
 import torch
 
-from ._lib import DotCfg, FFError, check, lib
+from ._lib import MATVEC_FAST, MATVEC_PLAIN, DotCfg, FFError, check, lib
 
 __all__ = [
     "lib", "FFError", "DotCfg", "build_info",
     "ff_add", "ff_sub", "ff_mul", "ff_mul_dekker", "ff_div", "ff_copy",
     "ff_dot_batched", "ff_dot_ff_batched", "ff_dot_batched_workspace_size",
+    "ff_sum_batched", "ff_sum_ff_batched",
+    "ff_matvec", "ff_matvec_backward", "ff_dot_backward", "MATVEC_FAST", "MATVEC_PLAIN",
     "ff_empty", "ff_zeros",
 ]
 
@@ -201,3 +203,131 @@ def ff_dot_ff_batched(x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, c
             xh, xl, yh, yl, ctypes.c_void_p(offsets.data_ptr()), nvec, total, _cfg_ptr(cfg),
             ctypes.c_void_p(ws.data_ptr()), ws.numel(), oh, ol, _stream_handle(stream)))
     return out
+
+
+def ff_sum_batched(x: torch.Tensor, offsets: torch.Tensor, cfg=None, out=None, workspace=None,
+                   stream=None) -> torch.Tensor:
+    """Float-float sums of binary32 segments [offsets[v], offsets[v+1]) of x
+    (Add22 accumulation).  Returns (2, nvec)."""
+    if x.dtype != torch.float32 or x.dim() != 1 or not x.is_contiguous() or not x.is_cuda:
+        raise ValueError("x: contiguous float32 vector on a HIP device expected")
+    nvec = _check_offsets(offsets, x.device)
+    out = ff_empty((nvec,), device=x.device) if out is None else out
+    _check_ff(out, "out")
+    ws = _workspace(ff_dot_batched_workspace_size(x.numel(), nvec, cfg), x.device, workspace)
+    oh, ol = _planes(out)
+    with torch.cuda.device(x.device):
+        check("ff_sum_batched", lib.ff_sum_batched(
+            ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), nvec, x.numel(),
+            _cfg_ptr(cfg), ctypes.c_void_p(ws.data_ptr()), ws.numel(), oh, ol,
+            _stream_handle(stream)))
+    return out
+
+
+def ff_sum_ff_batched(x: torch.Tensor, offsets: torch.Tensor, cfg=None, out=None,
+                      workspace=None, stream=None) -> torch.Tensor:
+    """Float-float sums of float-float segments of x (shape (2, total))."""
+    _check_ff(x, "x")
+    if x.dim() != 2:
+        raise ValueError("x must have shape (2, total)")
+    nvec = _check_offsets(offsets, x.device)
+    out = ff_empty((nvec,), device=x.device) if out is None else out
+    _check_ff(out, "out")
+    total = x.shape[1]
+    ws = _workspace(ff_dot_batched_workspace_size(total, nvec, cfg), x.device, workspace)
+    xh, xl = _planes(x)
+    oh, ol = _planes(out)
+    with torch.cuda.device(x.device):
+        check("ff_sum_ff_batched", lib.ff_sum_ff_batched(
+            xh, xl, ctypes.c_void_p(offsets.data_ptr()), nvec, total, _cfg_ptr(cfg),
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), oh, ol, _stream_handle(stream)))
+    return out
+
+
+# ------------------------------------------------------------ differentiation
+
+def _null():
+    return ctypes.c_void_p(0)
+
+
+def _check_matrix(A: torch.Tensor):
+    """A float-float matrix (2, M, N): each plane row-major with unit column
+    stride and a common leading dimension (row stride) >= N."""
+    if not isinstance(A, torch.Tensor) or A.dtype != torch.float32:
+        raise TypeError("A: expected a float32 tensor")
+    if A.dim() != 3 or A.shape[0] != 2:
+        raise ValueError(f"A must have shape (2, M, N), got {tuple(A.shape)}")
+    if not A.is_cuda:
+        raise ValueError("A: must be on a HIP device (libff runs on the GPU only)")
+    M, N = A.shape[1], A.shape[2]
+    if (N > 1 and A.stride(2) != 1) or (M > 1 and A.stride(1) < N):
+        raise ValueError("A: each plane must be row-major with unit column stride")
+    lda = A.stride(1) if M > 1 else max(N, 1)
+    return M, N, lda
+
+
+def ff_matvec(A: torch.Tensor, x: torch.Tensor, algo: int = MATVEC_FAST, out=None,
+              stream=None) -> torch.Tensor:
+    """y = A x for a float-float matrix A (2, M, N) and vector x (2, N)."""
+    M, N, lda = _check_matrix(A)
+    _check_ff(x, "x")
+    if x.shape != (2, N):
+        raise ValueError(f"x must have shape (2, {N})")
+    out = ff_empty((M,), device=A.device) if out is None else out
+    _check_ff(out, "out")
+    Ah, Al = _planes(A)
+    xh, xl = _planes(x)
+    yh, yl = _planes(out)
+    with torch.cuda.device(A.device):
+        check("ff_matvec", lib.ff_matvec(M, N, Ah, Al, lda, xh, xl, yh, yl, int(algo),
+                                         _stream_handle(stream)))
+    return out
+
+
+def ff_matvec_backward(A: torch.Tensor, x: torch.Tensor, g: torch.Tensor, want_dA: bool = True,
+                       want_dx: bool = True, algo: int = MATVEC_FAST, stream=None):
+    """Backward pass of y = A x for the upstream float-float gradient g (2, M):
+    returns (dA, dx) = (g x^T, A^T g); a gradient not wanted is None."""
+    M, N, lda = _check_matrix(A)
+    _check_ff(x, "x")
+    _check_ff(g, "g")
+    if x.shape != (2, N) or g.shape != (2, M):
+        raise ValueError("shape mismatch between A, x and g")
+    dA = ff_empty((M, N), device=A.device) if want_dA else None
+    dx = ff_empty((N,), device=A.device) if want_dx else None
+    nbytes = int(lib.ff_matvec_backward_workspace_size(M, N, int(algo))) if want_dx else 0
+    ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=A.device)
+    Ah, Al = _planes(A)
+    xh, xl = _planes(x)
+    gh, gl = _planes(g)
+    dAh, dAl = _planes(dA) if want_dA else (_null(), _null())
+    dxh, dxl = _planes(dx) if want_dx else (_null(), _null())
+    with torch.cuda.device(A.device):
+        check("ff_matvec_backward", lib.ff_matvec_backward(
+            M, N, Ah, Al, lda, xh, xl, gh, gl, dAh, dAl, N, dxh, dxl, int(algo),
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
+    return dA, dx
+
+
+def ff_dot_backward(g: torch.Tensor, x: torch.Tensor, y: torch.Tensor, want_dx: bool = True,
+                    want_dy: bool = True, stream=None):
+    """Backward pass of s = sum x_i y_i for an upstream float-float gradient
+    g (shape (2,) or (2, 1)): returns (g y, g x) (elementwise Mul22)."""
+    _check_ff(g, "g")
+    _check_ff(x, "x")
+    _check_ff(y, "y")
+    if g[0].numel() != 1 or x.shape != y.shape:
+        raise ValueError("g must hold one float-float value and x, y agree in shape")
+    n = x[0].numel()
+    dx = torch.empty_like(x) if want_dx else None
+    dy = torch.empty_like(y) if want_dy else None
+    g = g.reshape(2, 1).contiguous()
+    gh, gl = _planes(g)
+    xh, xl = _planes(x)
+    yh, yl = _planes(y)
+    dxh, dxl = _planes(dx) if want_dx else (_null(), _null())
+    dyh, dyl = _planes(dy) if want_dy else (_null(), _null())
+    with torch.cuda.device(x.device):
+        check("ff_dot_backward", lib.ff_dot_backward(gh, gl, xh, xl, yh, yl, dxh, dxl, dyh, dyl, n,
+                                                     _stream_handle(stream)))
+    return dx, dy

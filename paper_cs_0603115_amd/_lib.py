@@ -47,7 +47,20 @@ SIGNATURES = {
                        _st),
     "ff_dot_ff_batched": ([_P, _P, _P, _P, _P, _i32, _i64, ctypes.POINTER(DotCfg), _P, _sz, _P,
                            _P, _P], _st),
+    "ff_sum_batched": ([_P, _P, _i32, _i64, ctypes.POINTER(DotCfg), _P, _sz, _P, _P, _P], _st),
+    "ff_sum_ff_batched": ([_P, _P, _P, _i32, _i64, ctypes.POINTER(DotCfg), _P, _sz, _P, _P, _P],
+                          _st),
+    "ff_dot_batched_autotune": ([_P, _P, _P, _i32, _i64, _P, _sz, _P, _P, _i32, _P,
+                                 ctypes.POINTER(DotCfg), ctypes.POINTER(ctypes.c_float)], _st),
+    "ff_matvec": ([_i64, _i64, _P, _P, _i64, _P, _P, _P, _P, _i32, _P], _st),
+    "ff_matvec_backward_workspace_size": ([_i64, _i64, _i32], _sz),
+    "ff_matvec_backward": ([_i64, _i64, _P, _P, _i64, _P, _P, _P, _P, _P, _P, _i64, _P, _P, _i32,
+                            _P, _sz, _P], _st),
+    "ff_dot_backward": ([_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _i64, _P], _st),
 }
+
+MATVEC_FAST = 0
+MATVEC_PLAIN = 1
 
 FF_OK = 0
 STATUS_NAMES = {0: "FF_OK", 1: "FF_ERR_NULL", 2: "FF_ERR_SIZE", 3: "FF_ERR_ALIGN",
@@ -68,7 +81,7 @@ def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"libff.so not found at {LIB_PATH}: build the HIP library first "
-            "(python -m paper_cs_0603115_amd.build, or __graft_entry__.build())")
+            "(python paper_cs_0603115_amd/build.py, or __graft_entry__.build())")
     handle = ctypes.CDLL(LIB_PATH)
     for name, (args, res) in SIGNATURES.items():
         fn = getattr(handle, name)

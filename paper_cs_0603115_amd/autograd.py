@@ -1,0 +1,62 @@
+"""torch.autograd.Function wrappers with hand-written float-float backward
+kernels.
+
+Gradient convention: a float-float tensor has shape (2, ...) and its value
+is plane 0 + plane 1.  The gradient autograd carries for it has the same
+shape and holds, as a float-float number, dL/d(value) -- the derivative with
+respect to the represented number (which is also the derivative with respect
+to either plane).  The backward kernels read and write gradients in that
+form.  A scalar float-float loss is seeded with the float-float one,
+``loss.backward(torch.tensor([1.0, 0.0], device=...))``.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import (MATVEC_FAST, ff_dot_backward, ff_dot_ff_batched, ff_matvec,
+               ff_matvec_backward)
+
+__all__ = ["FFMatVec", "FFDot", "ff_one"]
+
+
+def ff_one(device="cuda") -> torch.Tensor:
+    """The float-float number 1 (seed for a scalar loss)."""
+    return torch.tensor([1.0, 0.0], dtype=torch.float32, device=device)
+
+
+class FFMatVec(torch.autograd.Function):
+    """y = A x (A: (2, M, N), x: (2, N), y: (2, M)); backward by
+    ff_matvec_backward: dA = g x^T, dx = A^T g."""
+
+    @staticmethod
+    def forward(ctx, A, x, algo=MATVEC_FAST):
+        ctx.save_for_backward(A, x)
+        ctx.algo = algo
+        return ff_matvec(A, x, algo=algo)
+
+    @staticmethod
+    def backward(ctx, gy):
+        A, x = ctx.saved_tensors
+        gy = gy.contiguous()
+        dA, dx = ff_matvec_backward(A, x, gy, want_dA=ctx.needs_input_grad[0],
+                                    want_dx=ctx.needs_input_grad[1], algo=ctx.algo)
+        return dA, dx, None
+
+
+class FFDot(torch.autograd.Function):
+    """s = sum_i u_i v_i for float-float vectors u, v (2, n); s has shape (2,).
+    Backward: du = g v, dv = g u (ff_dot_backward)."""
+
+    @staticmethod
+    def forward(ctx, u, v):
+        ctx.save_for_backward(u, v)
+        n = u.shape[1]
+        offsets = torch.tensor([0, n], dtype=torch.int64, device=u.device)
+        return ff_dot_ff_batched(u, v, offsets).reshape(2)
+
+    @staticmethod
+    def backward(ctx, gs):
+        u, v = ctx.saved_tensors
+        du, dv = ff_dot_backward(gs.contiguous(), u, v, want_dx=ctx.needs_input_grad[0],
+                                 want_dy=ctx.needs_input_grad[1])
+        return du, dv

@@ -4,7 +4,9 @@ Every HIP source under ``csrc/`` is compiled with hipcc, in parallel, into
 ``_build/`` and linked in place next to this file, so that the library
 travels with the source tree.  No GPU is needed: hipcc cross-compiles.
 
-    python -m paper_cs_0603115_amd.build
+    python paper_cs_0603115_amd/build.py
+
+(Run it as a file: importing the package loads the library being built.)
 """
 from __future__ import annotations
 

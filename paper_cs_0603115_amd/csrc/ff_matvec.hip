@@ -1,0 +1,426 @@
+// ff_matvec.hip -- float-float matrix-vector product y = A x, its backward
+// pass (dA = g x^T, dx = A^T g) and the backward pass of the float-float dot.
+//
+// A is M x N, row-major, hi and lo planes with leading dimension lda.  The
+// forward pass reads A once (8 bytes per element) and performs Mul22 + Add22
+// (~26 VALU) per element; the fused backward reads A once and writes dA once
+// (16 bytes per element) with Mul22 (dA) + Mul22 + Add22 (dx) (~38 VALU).
+// Both are HBM-bound on gfx950 (ridge ~4.9 lane-ops per byte).
+//
+// Fast forward: one workgroup per row; lane t takes float4 groups t,
+// t + BLOCK, ... of the row (coalesced 1 KiB per wavefront load), keeps four
+// Add22 accumulators (one per float4 component), then a wavefront butterfly
+// and an in-order LDS combine give y_i.  x is re-read from L2 by every row.
+// Fast backward: the workgroup grid is (column tiles) x (row bands); a
+// thread owns four adjacent columns, walks the rows of its band, writes
+// dA_ij = Mul22(g_i, x_j) and accumulates Mul22(g_i, A_ij) per column; the
+// per-band partial column sums go to the workspace and a second launch adds
+// them in band order.
+#include "ff_device.h"
+#include "ff_host.h"
+
+namespace ffk {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kRowBlock = 256;
+constexpr int kColBlock = 256;
+constexpr int64_t kBandRows = 64;
+
+template <int BLOCK, bool VEC>
+__global__ __launch_bounds__(BLOCK) void matvec_rows(int64_t M, int64_t N,
+                                                     const float *__restrict__ Ah,
+                                                     const float *__restrict__ Al, int64_t lda,
+                                                     const float *__restrict__ xh,
+                                                     const float *__restrict__ xl,
+                                                     float *__restrict__ yh, float *__restrict__ yl)
+{
+    constexpr int kWaves = BLOCK / 64;
+    __shared__ float2 part[kWaves];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int64_t r = blockIdx.x; r < M; r += gridDim.x) {
+        const float *rh = Ah + r * lda;
+        const float *rl = Al + r * lda;
+        float2 acc[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            acc[k] = make_float2(0.0f, 0.0f);
+        int64_t j_scalar = tid;
+        if (VEC) {
+            const int64_t ng = N >> 2;
+            const f32x4 *rh4 = reinterpret_cast<const f32x4 *>(rh);
+            const f32x4 *rl4 = reinterpret_cast<const f32x4 *>(rl);
+            const f32x4 *xh4 = reinterpret_cast<const f32x4 *>(xh);
+            const f32x4 *xl4 = reinterpret_cast<const f32x4 *>(xl);
+            for (int64_t g = tid; g < ng; g += BLOCK) {
+                const f32x4 ah = __builtin_nontemporal_load(rh4 + g);
+                const f32x4 al = __builtin_nontemporal_load(rl4 + g);
+                const f32x4 bh = xh4[g], bl = xl4[g];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    float ph, pl;
+                    ffd::mul22<false>(ah[k], al[k], bh[k], bl[k], ph, pl);
+                    ffd::add22(acc[k].x, acc[k].y, ph, pl, acc[k].x, acc[k].y);
+                }
+            }
+            j_scalar = 4 * ng + tid;
+        }
+        for (int64_t j = j_scalar; j < N; j += BLOCK) {
+            float ph, pl;
+            ffd::mul22<false>(rh[j], rl[j], xh[j], xl[j], ph, pl);
+            ffd::add22(acc[0].x, acc[0].y, ph, pl, acc[0].x, acc[0].y);
+        }
+        float h = acc[0].x, l = acc[0].y, h2 = acc[2].x, l2 = acc[2].y;
+        ffd::add22(h, l, acc[1].x, acc[1].y, h, l);
+        ffd::add22(h2, l2, acc[3].x, acc[3].y, h2, l2);
+        ffd::add22(h, l, h2, l2, h, l);
+        ffd::wave_allreduce_add22(h, l);
+        if (lane == 0)
+            part[wave] = make_float2(h, l);
+        __syncthreads();
+        if (tid == 0) {
+            float th = part[0].x, tl = part[0].y;
+#pragma unroll
+            for (int k = 1; k < kWaves; ++k)
+                ffd::add22(th, tl, part[k].x, part[k].y, th, tl);
+            yh[r] = th;
+            yl[r] = tl;
+        }
+        __syncthreads();
+    }
+}
+
+// Plain forward: one thread per row, terms added in column order.
+__global__ __launch_bounds__(256) void matvec_plain(int64_t M, int64_t N,
+                                                    const float *__restrict__ Ah,
+                                                    const float *__restrict__ Al, int64_t lda,
+                                                    const float *__restrict__ xh,
+                                                    const float *__restrict__ xl,
+                                                    float *__restrict__ yh, float *__restrict__ yl)
+{
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (r >= M)
+        return;
+    float h = 0.0f, l = 0.0f;
+    for (int64_t j = 0; j < N; ++j) {
+        float ph, pl;
+        ffd::mul22<false>(Ah[r * lda + j], Al[r * lda + j], xh[j], xl[j], ph, pl);
+        ffd::add22(h, l, ph, pl, h, l);
+    }
+    yh[r] = h;
+    yl[r] = l;
+}
+
+// Fused backward over one row band: thread owns COLS adjacent columns.
+template <int BLOCK, int COLS, bool WANT_DA, bool WANT_DX>
+__global__ __launch_bounds__(BLOCK) void matvec_bwd_band(
+    int64_t M, int64_t N, const float *__restrict__ Ah, const float *__restrict__ Al, int64_t lda,
+    const float *__restrict__ xh, const float *__restrict__ xl, const float *__restrict__ gh,
+    const float *__restrict__ gl, float *__restrict__ dAh, float *__restrict__ dAl, int64_t ldda,
+    float2 *__restrict__ part)
+{
+    const int64_t c0 = (static_cast<int64_t>(blockIdx.x) * BLOCK + threadIdx.x) * COLS;
+    if (c0 >= N)
+        return;
+    const int64_t i0 = static_cast<int64_t>(blockIdx.y) * kBandRows;
+    const int64_t i1 = (i0 + kBandRows < M) ? i0 + kBandRows : M;
+    float x_h[COLS], x_l[COLS];
+    float2 acc[COLS];
+#pragma unroll
+    for (int k = 0; k < COLS; ++k) {
+        acc[k] = make_float2(0.0f, 0.0f);
+        if (WANT_DA) {
+            x_h[k] = xh[c0 + k];
+            x_l[k] = xl[c0 + k];
+        }
+    }
+    for (int64_t i = i0; i < i1; ++i) {
+        const float g_h = gh[i], g_l = gl[i];
+        float a_h[COLS], a_l[COLS];
+        if (WANT_DX) {
+            if constexpr (COLS == 4) {
+                const f32x4 vh = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Ah + i * lda + c0));
+                const f32x4 vl = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Al + i * lda + c0));
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    a_h[k] = vh[k];
+                    a_l[k] = vl[k];
+                }
+            } else {
+                a_h[0] = Ah[i * lda + c0];
+                a_l[0] = Al[i * lda + c0];
+            }
+        }
+        if (WANT_DA) {
+            float d_h[COLS], d_l[COLS];
+#pragma unroll
+            for (int k = 0; k < COLS; ++k)
+                ffd::mul22<false>(g_h, g_l, x_h[k], x_l[k], d_h[k], d_l[k]);
+            if constexpr (COLS == 4) {
+                const f32x4 vh = {d_h[0], d_h[1], d_h[2], d_h[3]};
+                const f32x4 vl = {d_l[0], d_l[1], d_l[2], d_l[3]};
+                __builtin_nontemporal_store(vh, reinterpret_cast<f32x4 *>(dAh + i * ldda + c0));
+                __builtin_nontemporal_store(vl, reinterpret_cast<f32x4 *>(dAl + i * ldda + c0));
+            } else {
+                dAh[i * ldda + c0] = d_h[0];
+                dAl[i * ldda + c0] = d_l[0];
+            }
+        }
+        if (WANT_DX) {
+#pragma unroll
+            for (int k = 0; k < COLS; ++k) {
+                float ph, pl;
+                ffd::mul22<false>(g_h, g_l, a_h[k], a_l[k], ph, pl);
+                ffd::add22(acc[k].x, acc[k].y, ph, pl, acc[k].x, acc[k].y);
+            }
+        }
+    }
+    if (WANT_DX) {
+#pragma unroll
+        for (int k = 0; k < COLS; ++k)
+            part[static_cast<int64_t>(blockIdx.y) * N + c0 + k] = acc[k];
+    }
+}
+
+// dx_j = partial sums of column j added in band order.
+__global__ __launch_bounds__(256) void matvec_bwd_combine(int64_t N, int64_t nbands,
+                                                          const float2 *__restrict__ part,
+                                                          float *__restrict__ dxh,
+                                                          float *__restrict__ dxl)
+{
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (j >= N)
+        return;
+    float h = 0.0f, l = 0.0f;
+    for (int64_t b = 0; b < nbands; ++b) {
+        const float2 p = part[b * N + j];
+        ffd::add22(h, l, p.x, p.y, h, l);
+    }
+    dxh[j] = h;
+    dxl[j] = l;
+}
+
+// Plain backward, dx: one thread per column, rows in order.
+__global__ __launch_bounds__(256) void matvec_bwd_plain_dx(
+    int64_t M, int64_t N, const float *__restrict__ Ah, const float *__restrict__ Al, int64_t lda,
+    const float *__restrict__ gh, const float *__restrict__ gl, float *__restrict__ dxh,
+    float *__restrict__ dxl)
+{
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (j >= N)
+        return;
+    float h = 0.0f, l = 0.0f;
+    for (int64_t i = 0; i < M; ++i) {
+        float ph, pl;
+        ffd::mul22<false>(gh[i], gl[i], Ah[i * lda + j], Al[i * lda + j], ph, pl);
+        ffd::add22(h, l, ph, pl, h, l);
+    }
+    dxh[j] = h;
+    dxl[j] = l;
+}
+
+// Plain backward, dA: one thread per element.
+__global__ __launch_bounds__(256) void matvec_bwd_plain_da(
+    int64_t M, int64_t N, const float *__restrict__ xh, const float *__restrict__ xl,
+    const float *__restrict__ gh, const float *__restrict__ gl, float *__restrict__ dAh,
+    float *__restrict__ dAl, int64_t ldda)
+{
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t i = blockIdx.y;
+    if (j >= N || i >= M)
+        return;
+    float h, l;
+    ffd::mul22<false>(gh[i], gl[i], xh[j], xl[j], h, l);
+    dAh[i * ldda + j] = h;
+    dAl[i * ldda + j] = l;
+}
+
+// Dot backward: dx_i = Mul22(g, y_i), dy_i = Mul22(g, x_i).
+__global__ __launch_bounds__(256) void dot_backward(const float *__restrict__ g_hi,
+                                                    const float *__restrict__ g_lo,
+                                                    const float *__restrict__ xh,
+                                                    const float *__restrict__ xl,
+                                                    const float *__restrict__ yh,
+                                                    const float *__restrict__ yl,
+                                                    float *__restrict__ dxh,
+                                                    float *__restrict__ dxl,
+                                                    float *__restrict__ dyh,
+                                                    float *__restrict__ dyl, int64_t n)
+{
+    const float gh = g_hi[0], gl = g_lo[0];
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * 256;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += stride) {
+        float h, l;
+        if (dxh) {
+            ffd::mul22<false>(gh, gl, yh[i], yl[i], h, l);
+            dxh[i] = h;
+            dxl[i] = l;
+        }
+        if (dyh) {
+            ffd::mul22<false>(gh, gl, xh[i], xl[i], h, l);
+            dyh[i] = h;
+            dyl[i] = l;
+        }
+    }
+}
+
+bool all_aligned(std::initializer_list<const void *> ptrs, uintptr_t bytes)
+{
+    for (const void *p : ptrs)
+        if (p && !ffh::aligned(p, bytes))
+            return false;
+    return true;
+}
+
+int64_t nbands_of(int64_t M) { return (M + kBandRows - 1) / kBandRows; }
+
+} // namespace ffk
+
+using namespace ffk;
+
+extern "C" {
+
+ff_status ff_matvec(int64_t M, int64_t N, const float *A_hi, const float *A_lo, int64_t lda,
+                    const float *x_hi, const float *x_lo, float *y_hi, float *y_lo, int32_t algo,
+                    void *stream)
+{
+    if (M < 0 || N < 0 || lda < N)
+        return FF_ERR_SIZE;
+    if (algo != FF_MATVEC_FAST && algo != FF_MATVEC_PLAIN)
+        return FF_ERR_ARG;
+    if (M == 0)
+        return FF_OK;
+    if (!y_hi || !y_lo || (N > 0 && (!A_hi || !A_lo || !x_hi || !x_lo)))
+        return FF_ERR_NULL;
+    if (!all_aligned({A_hi, A_lo, x_hi, x_lo, y_hi, y_lo}, 4))
+        return FF_ERR_ALIGN;
+    if (M > INT32_MAX)
+        return FF_ERR_SIZE;
+    hipStream_t st = ffh::as_stream(stream);
+    if (algo == FF_MATVEC_PLAIN) {
+        hipLaunchKernelGGL(matvec_plain, dim3(static_cast<unsigned>(ffh::cdiv(M, 256))), dim3(256),
+                           0, st, M, N, A_hi, A_lo, lda, x_hi, x_lo, y_hi, y_lo);
+    } else {
+        const bool vec = all_aligned({A_hi, A_lo, x_hi, x_lo}, 16) && lda % 4 == 0;
+        if (vec)
+            hipLaunchKernelGGL((matvec_rows<kRowBlock, true>), dim3(static_cast<unsigned>(M)),
+                               dim3(kRowBlock), 0, st, M, N, A_hi, A_lo, lda, x_hi, x_lo, y_hi,
+                               y_lo);
+        else
+            hipLaunchKernelGGL((matvec_rows<kRowBlock, false>), dim3(static_cast<unsigned>(M)),
+                               dim3(kRowBlock), 0, st, M, N, A_hi, A_lo, lda, x_hi, x_lo, y_hi,
+                               y_lo);
+    }
+    return ffh::launch_status();
+}
+
+size_t ff_matvec_backward_workspace_size(int64_t M, int64_t N, int32_t algo)
+{
+    if (M < 0 || N < 0 || algo != FF_MATVEC_FAST)
+        return 0;
+    return static_cast<size_t>(nbands_of(M)) * static_cast<size_t>(N) * sizeof(float2);
+}
+
+ff_status ff_matvec_backward(int64_t M, int64_t N, const float *A_hi, const float *A_lo,
+                             int64_t lda, const float *x_hi, const float *x_lo, const float *g_hi,
+                             const float *g_lo, float *dA_hi, float *dA_lo, int64_t ldda,
+                             float *dx_hi, float *dx_lo, int32_t algo, void *ws, size_t ws_bytes,
+                             void *stream)
+{
+    if (M < 0 || N < 0 || lda < N)
+        return FF_ERR_SIZE;
+    if (algo != FF_MATVEC_FAST && algo != FF_MATVEC_PLAIN)
+        return FF_ERR_ARG;
+    const bool want_da = dA_hi || dA_lo;
+    const bool want_dx = dx_hi || dx_lo;
+    if ((want_da && (!dA_hi || !dA_lo)) || (want_dx && (!dx_hi || !dx_lo)))
+        return FF_ERR_NULL;
+    if (want_da && ldda < N)
+        return FF_ERR_SIZE;
+    if (N == 0 || (!want_da && !want_dx))
+        return FF_OK;
+    if ((M > 0 && (!g_hi || !g_lo)) || (want_da && (!x_hi || !x_lo)) ||
+        (want_dx && M > 0 && (!A_hi || !A_lo)))
+        return FF_ERR_NULL;
+    if (!all_aligned({A_hi, A_lo, x_hi, x_lo, g_hi, g_lo, dA_hi, dA_lo, dx_hi, dx_lo}, 4))
+        return FF_ERR_ALIGN;
+    if (M > 65535 * kBandRows || M > INT32_MAX)
+        return FF_ERR_SIZE;
+    hipStream_t st = ffh::as_stream(stream);
+    if (algo == FF_MATVEC_PLAIN) {
+        if (want_da && M > 65535)
+            return FF_ERR_SIZE;
+        if (want_da && M > 0)
+            hipLaunchKernelGGL(matvec_bwd_plain_da,
+                               dim3(static_cast<unsigned>(ffh::cdiv(N, 256)), static_cast<unsigned>(M)),
+                               dim3(256), 0, st, M, N, x_hi, x_lo, g_hi, g_lo, dA_hi, dA_lo, ldda);
+        if (want_dx)
+            hipLaunchKernelGGL(matvec_bwd_plain_dx, dim3(static_cast<unsigned>(ffh::cdiv(N, 256))),
+                               dim3(256), 0, st, M, N, A_hi, A_lo, lda, g_hi, g_lo, dx_hi, dx_lo);
+        return ffh::launch_status();
+    }
+    const int64_t nbands = nbands_of(M);
+    if (want_dx && M > 0) {
+        if (!ws)
+            return FF_ERR_NULL;
+        if (ws_bytes < ff_matvec_backward_workspace_size(M, N, algo))
+            return FF_ERR_WORKSPACE;
+        if (!ffh::aligned(ws, 16))
+            return FF_ERR_ALIGN;
+    }
+    float2 *part = static_cast<float2 *>(ws);
+    if (M > 0) {
+        const bool vec = N % 4 == 0 && lda % 4 == 0 && (!want_da || ldda % 4 == 0) &&
+                         all_aligned({A_hi, A_lo, dA_hi, dA_lo}, 16);
+        const int cols = vec ? 4 : 1;
+        const dim3 grid(static_cast<unsigned>(ffh::cdiv(N, int64_t(kColBlock) * cols)),
+                        static_cast<unsigned>(nbands));
+#define FF_BWD_LAUNCH(C, DA, DX)                                                               \
+    hipLaunchKernelGGL((matvec_bwd_band<kColBlock, C, DA, DX>), grid, dim3(kColBlock), 0, st, M, \
+                       N, A_hi, A_lo, lda, x_hi, x_lo, g_hi, g_lo, dA_hi, dA_lo, ldda, part)
+        if (vec) {
+            if (want_da && want_dx)
+                FF_BWD_LAUNCH(4, true, true);
+            else if (want_da)
+                FF_BWD_LAUNCH(4, true, false);
+            else
+                FF_BWD_LAUNCH(4, false, true);
+        } else {
+            if (want_da && want_dx)
+                FF_BWD_LAUNCH(1, true, true);
+            else if (want_da)
+                FF_BWD_LAUNCH(1, true, false);
+            else
+                FF_BWD_LAUNCH(1, false, true);
+        }
+#undef FF_BWD_LAUNCH
+    }
+    if (want_dx)
+        hipLaunchKernelGGL(matvec_bwd_combine, dim3(static_cast<unsigned>(ffh::cdiv(N, 256))),
+                           dim3(256), 0, st, N, nbands, part, dx_hi, dx_lo);
+    return ffh::launch_status();
+}
+
+ff_status ff_dot_backward(const float *g_hi, const float *g_lo, const float *x_hi,
+                          const float *x_lo, const float *y_hi, const float *y_lo, float *dx_hi,
+                          float *dx_lo, float *dy_hi, float *dy_lo, int64_t n, void *stream)
+{
+    if (n < 0)
+        return FF_ERR_SIZE;
+    const bool want_dx = dx_hi || dx_lo, want_dy = dy_hi || dy_lo;
+    if ((want_dx && (!dx_hi || !dx_lo)) || (want_dy && (!dy_hi || !dy_lo)))
+        return FF_ERR_NULL;
+    if (n == 0 || (!want_dx && !want_dy))
+        return FF_OK;
+    if (!g_hi || !g_lo || (want_dx && (!y_hi || !y_lo)) || (want_dy && (!x_hi || !x_lo)))
+        return FF_ERR_NULL;
+    if (!all_aligned({g_hi, g_lo, x_hi, x_lo, y_hi, y_lo, dx_hi, dx_lo, dy_hi, dy_lo}, 4))
+        return FF_ERR_ALIGN;
+    const int64_t blocks = ffh::cdiv(n, 256);
+    hipLaunchKernelGGL(dot_backward, dim3(static_cast<unsigned>(blocks < 65536 ? blocks : 65536)),
+                       dim3(256), 0, ffh::as_stream(stream), g_hi, g_lo, x_hi, x_lo, y_hi, y_lo,
+                       want_dx ? dx_hi : nullptr, dx_lo, want_dy ? dy_hi : nullptr, dy_lo, n);
+    return ffh::launch_status();
+}
+
+} // extern "C"

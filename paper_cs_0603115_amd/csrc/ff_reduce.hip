@@ -133,6 +133,14 @@ struct InFF {
     const float *xh, *xl, *yh, *yl;
     static constexpr int kBytes = 16;
 };
+struct InSumF32 {
+    const float *x;
+    static constexpr int kBytes = 4;
+};
+struct InSumFF {
+    const float *xh, *xl;
+    static constexpr int kBytes = 8;
+};
 
 __device__ __forceinline__ void accumulate_term(float &h, float &l, float ph, float pl)
 {
@@ -214,6 +222,63 @@ struct Terms<InFF> {
         float ph, pl;
         ffd::mul22<false>(in.xh[i], in.xl[i], in.yh[i], in.yl[i], ph, pl);
         accumulate_term(acc.x, acc.y, ph, pl);
+    }
+};
+
+template <>
+struct Terms<InSumF32> {
+    // term = (x_i, 0): the binary32 value itself
+    __device__ __forceinline__ static void group(const InSumF32 &in, int64_t g, int64_t s,
+                                                 int64_t e, int64_t total, float2 acc[4])
+    {
+        const int64_t i0 = 4 * g;
+        f32x4 x;
+        if (i0 + 4 <= total) {
+            x = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(in.x) + g);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                x[k] = i0 + k < total ? in.x[i0 + k] : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool on = (i0 + k >= s) && (i0 + k < e);
+            accumulate_term(acc[k].x, acc[k].y, on ? x[k] : 0.0f, 0.0f);
+        }
+    }
+    __device__ __forceinline__ static void one(const InSumF32 &in, int64_t i, float2 &acc)
+    {
+        accumulate_term(acc.x, acc.y, in.x[i], 0.0f);
+    }
+};
+
+template <>
+struct Terms<InSumFF> {
+    __device__ __forceinline__ static void group(const InSumFF &in, int64_t g, int64_t s,
+                                                 int64_t e, int64_t total, float2 acc[4])
+    {
+        const int64_t i0 = 4 * g;
+        f32x4 xh, xl;
+        if (i0 + 4 <= total) {
+            xh = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(in.xh) + g);
+            xl = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(in.xl) + g);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const bool in_range = i0 + k < total;
+                xh[k] = in_range ? in.xh[i0 + k] : 0.0f;
+                xl[k] = in_range ? in.xl[i0 + k] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool on = (i0 + k >= s) && (i0 + k < e);
+            accumulate_term(acc[k].x, acc[k].y, on ? xh[k] : 0.0f, on ? xl[k] : 0.0f);
+        }
+    }
+    __device__ __forceinline__ static void one(const InSumFF &in, int64_t i, float2 &acc)
+    {
+        accumulate_term(acc.x, acc.y, in.xh[i], in.xl[i]);
     }
 };
 
@@ -441,6 +506,102 @@ ff_status ff_dot_ff_batched(const float *x_hi, const float *x_lo, const float *y
     }
     return dot_batched_entry(InFF{x_hi, x_lo, y_hi, y_lo}, vec, offsets, nvec, total_len, cfg, ws,
                              ws_bytes, out_hi, out_lo, stream);
+}
+
+ff_status ff_sum_batched(const float *x, const int64_t *offsets, int32_t nvec, int64_t total_len,
+                         const ff_dot_cfg *cfg, void *ws, size_t ws_bytes, float *out_hi,
+                         float *out_lo, void *stream)
+{
+    if (nvec < 0 || total_len < 0)
+        return FF_ERR_SIZE;
+    if (total_len > 0 && !x)
+        return FF_ERR_NULL;
+    if (!ffh::aligned(x, 4))
+        return FF_ERR_ALIGN;
+    return dot_batched_entry(InSumF32{x}, ffh::aligned(x, 16), offsets, nvec, total_len, cfg, ws,
+                             ws_bytes, out_hi, out_lo, stream);
+}
+
+ff_status ff_sum_ff_batched(const float *x_hi, const float *x_lo, const int64_t *offsets,
+                            int32_t nvec, int64_t total_len, const ff_dot_cfg *cfg, void *ws,
+                            size_t ws_bytes, float *out_hi, float *out_lo, void *stream)
+{
+    if (nvec < 0 || total_len < 0)
+        return FF_ERR_SIZE;
+    if (total_len > 0 && (!x_hi || !x_lo))
+        return FF_ERR_NULL;
+    if (!ffh::aligned(x_hi, 4) || !ffh::aligned(x_lo, 4))
+        return FF_ERR_ALIGN;
+    const bool vec = ffh::aligned(x_hi, 16) && ffh::aligned(x_lo, 16);
+    return dot_batched_entry(InSumFF{x_hi, x_lo}, vec, offsets, nvec, total_len, cfg, ws, ws_bytes,
+                             out_hi, out_lo, stream);
+}
+
+ff_status ff_dot_batched_autotune(const float *x, const float *y, const int64_t *offsets,
+                                  int32_t nvec, int64_t total_len, void *ws, size_t ws_bytes,
+                                  float *out_hi, float *out_lo, int32_t reps, void *stream,
+                                  ff_dot_cfg *best, float *best_ms)
+{
+    if (!best || !best_ms)
+        return FF_ERR_NULL;
+    if (reps < 1)
+        return FF_ERR_ARG;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return ffh::hip_failure(hipGetLastError());
+    static const int kBlocks[] = {256, 512};
+    static const int kUnrolls[] = {1, 2, 4};
+    static const int kChunks[] = {4096, 8192, 16384, 32768, 65536};
+    static const int kPerCu[] = {2, 4, 8, 16};
+    hipStream_t st = ffh::as_stream(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess)
+        return ffh::hip_failure(hipGetLastError());
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return ffh::hip_failure(hipGetLastError());
+    }
+    ff_status status = FF_OK;
+    float best_time = -1.0f;
+    for (int blk : kBlocks)
+        for (int un : kUnrolls)
+            for (int ch : kChunks)
+                for (int pc : kPerCu) {
+                    ff_dot_cfg c{blk, ch, pc * cus, un};
+                    if (ff_dot_batched_workspace_size(total_len, nvec, &c) > ws_bytes)
+                        continue;
+                    // one untimed launch, then reps timed launches
+                    status = ff_dot_batched(x, y, offsets, nvec, total_len, &c, ws, ws_bytes,
+                                            out_hi, out_lo, stream);
+                    if (status != FF_OK)
+                        goto done;
+                    hipEventRecord(e0, st);
+                    for (int r = 0; r < reps && status == FF_OK; ++r)
+                        status = ff_dot_batched(x, y, offsets, nvec, total_len, &c, ws, ws_bytes,
+                                                out_hi, out_lo, stream);
+                    hipEventRecord(e1, st);
+                    if (status != FF_OK)
+                        goto done;
+                    if (hipEventSynchronize(e1) != hipSuccess) {
+                        status = ffh::hip_failure(hipGetLastError());
+                        goto done;
+                    }
+                    float ms = 0.0f;
+                    hipEventElapsedTime(&ms, e0, e1);
+                    ms /= reps;
+                    if (best_time < 0.0f || ms < best_time) {
+                        best_time = ms;
+                        *best = c;
+                    }
+                }
+    if (best_time < 0.0f)
+        status = FF_ERR_WORKSPACE;
+    *best_ms = best_time;
+done:
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return status;
 }
 
 } // extern "C"

@@ -157,3 +157,48 @@ def test_dot_validation(name):
     assert call(planes=p) == ERR_ALIGN
     assert call(offs=offs + 4) == ERR_ALIGN
     assert call(ws=ws + 64) == ERR_ALIGN
+
+
+def test_matvec_validation():
+    mv = ff.lib.ff_matvec
+    A = [4096, 8192]
+    x = [12288, 16384]
+    y = [20480, 24576]
+    assert mv(-1, 4, *A, 4, *x, *y, 0, None) == ERR_SIZE
+    assert mv(4, 4, *A, 3, *x, *y, 0, None) == ERR_SIZE       # lda < N
+    assert mv(4, 4, *A, 4, *x, *y, 2, None) == ERR_ARG        # unknown algo
+    assert mv(0, 4, *A, 4, *x, *y, 0, None) == 0              # nothing to do
+    assert mv(4, 4, None, A[1], 4, *x, *y, 0, None) == ERR_NULL
+    assert mv(4, 4, *A, 4, *x, y[0] + 2, y[1], 0, None) == ERR_ALIGN
+    bw = ff.lib.ff_matvec_backward
+    g = [28672, 32768]
+    dA = [36864, 40960]
+    dx = [45056, 49152]
+    need = ff.lib.ff_matvec_backward_workspace_size(100, 4, 0)
+    assert need == 2 * 4 * 8                                  # 2 bands x 4 columns x float2
+    assert ff.lib.ff_matvec_backward_workspace_size(100, 4, 1) == 0
+    ws = 1 << 20
+    assert bw(100, 4, *A, 4, *x, *g, *dA, 4, *dx, 0, ws, need - 1, None) == ERR_WS
+    assert bw(100, 4, *A, 4, *x, *g, *dA, 3, *dx, 0, ws, need, None) == ERR_SIZE
+    assert bw(100, 4, *A, 4, *x, *g, dA[0], None, 4, *dx, 0, ws, need, None) == ERR_NULL
+    assert bw(100, 4, *A, 4, *x, *g, None, None, 4, None, None, 0, ws, need, None) == 0
+    assert bw(100, 4, *A, 4, *x, *g, *dA, 4, *dx, 5, ws, need, None) == ERR_ARG
+    db = ff.lib.ff_dot_backward
+    assert db(*g, *x, *y, *dx, *dA, -1, None) == ERR_SIZE
+    assert db(*g, *x, *y, *dx, *dA, 0, None) == 0
+    assert db(None, g[1], *x, *y, *dx, *dA, 8, None) == ERR_NULL
+    assert db(*g, *x, *y, dx[0], None, *dA, 8, None) == ERR_NULL
+
+
+def test_sum_and_autotune_validation():
+    assert ff.lib.ff_sum_batched(4096, 8192, -1, 10, None, 1 << 20, 1 << 16, 1 << 21, 1 << 22,
+                                 None) == ERR_SIZE
+    assert ff.lib.ff_sum_ff_batched(4096, 4098, 8192, 2, 10, None, 1 << 20, 1 << 16, 1 << 21,
+                                    1 << 22, None) == ERR_ALIGN
+    best = _lib.DotCfg()
+    ms = ctypes.c_float()
+    assert ff.lib.ff_dot_batched_autotune(4096, 8192, 12288, 4, 100, 1 << 20, 1 << 16, 1 << 21,
+                                          1 << 22, 0, None, ctypes.byref(best),
+                                          ctypes.byref(ms)) == ERR_ARG
+    assert ff.lib.ff_dot_batched_autotune(4096, 8192, 12288, 4, 100, 1 << 20, 1 << 16, 1 << 21,
+                                          1 << 22, 3, None, None, ctypes.byref(ms)) == ERR_NULL

@@ -167,3 +167,48 @@ def test_full_batch_4096_vectors():
     _announce(f"  worst normwise log2 error {worst:.1f}")
     del x, y
     torch.cuda.empty_cache()
+
+
+def test_batched_sums_binary32_and_float_float():
+    _announce("[gpu] sum batched")
+    ff = _ff()
+    x, _, offs = fi.batched_dot(7, nvec=200, max_total=1 << 21)
+    got = ff.ff_sum_batched(x.cuda(), offs.cuda()).cpu().numpy()
+    xn, on = x.numpy(), offs.numpy()
+    ones = np.ones_like(xn)
+    exact = oracle.exact_dot_batched(xn, ones, on)
+    absum = oracle.exact_dot_batched(np.abs(xn), ones, on)
+    for v in range(200):
+        err = abs(frac(got[0, v]) + frac(got[1, v]) - exact[v])
+        assert err <= TWO_M44 * absum[v]
+    a = fi.gaussian_ff((1 << 20,), 8)
+    lens = torch.tensor([5, 1000, 300000, 0, 12345])
+    lens = torch.cat([lens, torch.tensor([(1 << 20) - int(lens.sum())])])
+    offs = torch.zeros(lens.numel() + 1, dtype=torch.int64)
+    offs[1:] = torch.cumsum(lens, 0)
+    got = ff.ff_sum_ff_batched(a.cuda(), offs.cuda()).cpu().numpy()
+    an, on = a.numpy(), offs.numpy()
+    one = np.ones(1 << 20, np.float32)
+    zero = np.zeros(1 << 20, np.float32)
+    for v in range(lens.numel()):
+        s, e = on[v], on[v + 1]
+        exact = oracle.exact_dot_ff(an[0, s:e], an[1, s:e], one[s:e], zero[s:e])
+        absum = oracle.exact_dot_ff(np.abs(an[0, s:e]), np.sign(an[0, s:e]) * an[1, s:e],
+                                    one[s:e], zero[s:e])
+        err = abs(frac(got[0, v]) + frac(got[1, v]) - exact)
+        assert err <= TWO_M44 * absum
+
+
+def test_autotuner_returns_a_valid_fast_shape(tmp_path, monkeypatch):
+    _announce("[gpu] dot autotune")
+    monkeypatch.setenv("FF_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    from paper_cs_0603115_amd import autotune
+    autotune._MEMO = None
+    x, y, offs = fi.batched_dot(115003, nvec=512, max_total=1 << 24, device="cuda")
+    cfg = autotune.dot_cfg(x, y, offs)
+    assert cfg[0] in (256, 512) and cfg[3] in (1, 2, 4) and cfg[1] % 4 == 0
+    assert (tmp_path / "tune.json").exists()
+    autotune._MEMO = None
+    assert autotune.dot_cfg(x, y, offs, search=False) == cfg      # served from the file
+    got = _ff().ff_dot_batched(x, y, offs, cfg=cfg)
+    check_against_exact(x, y, offs, got, cfg, "tuned")
