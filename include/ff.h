@@ -270,6 +270,54 @@ ff_status ff_dot_backward(const float *g_hi, const float *g_lo,
                           void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Matrix product C = A B                                                   */
+/* ------------------------------------------------------------------------ */
+/*
+ * A (M x K), B (K x N), C (M x N): float-float, row-major, two planes each
+ * with leading dimensions lda >= K, ldb >= N, ldc >= N.  C is overwritten.
+ * The paper defines no matrix product; both algorithms build on its
+ * operators and error-free transformations.
+ *
+ * FF_GEMM_FMA_LOOP    the plain float-float GEMM: C_ij = Add22
+ *                     accumulation, k ascending, of Mul22(A_ik, B_kj)
+ *                     (section 4.1).  Bit-identical to that definition.
+ * FF_GEMM_SLICED_I8   matrix-core path: each row of A and column of B is
+ *                     scaled by a power of two and cut into 7 signed 8-bit
+ *                     digits; the 28 digit-pair products that carry weight
+ *                     above 2^-56 of the row/column scales run as exact
+ *                     integer GEMMs (int8 inputs, int32 accumulation) and
+ *                     are recombined exactly; one final rounding to
+ *                     float-float.  No binary64 arithmetic.
+ * FF_GEMM_SLICED_BF16 as above with the digits held in BF16 (exact for
+ *                     |d| <= 128) and FP32 matrix-core accumulation, whose
+ *                     partial sums are moved to integer accumulators before
+ *                     they can exceed 2^24 (so they stay exact).
+ * Sliced accuracy: |C_ij - exact| <= 2^-44 * (|A| |B|)_ij for inputs whose
+ * rows/columns do not span extreme dynamic ranges (the digit rounding
+ * contributes at most 2^(e_i - 54) sum_k |B_kj| + 2^(f_j - 54) sum_k |A_ik|,
+ * with 2^e_i the power of two above row i's largest |A_ik|, 2^f_j likewise).
+ * Inputs must be finite float-float numbers with |lo| <= ulp(hi).
+ * Workspace: 0 bytes for the FMA loop; digit planes (7 (M+N) K bytes for
+ * int8, twice that for BF16, rounded up to 64-row / 64-byte tiles) plus
+ * scales for the sliced paths.
+ * Errors: FF_ERR_SIZE, FF_ERR_NULL, FF_ERR_ALIGN, FF_ERR_ARG (algo),
+ * FF_ERR_WORKSPACE, FF_ERR_HIP.
+ */
+#define FF_GEMM_FMA_LOOP    0
+#define FF_GEMM_SLICED_BF16 1
+#define FF_GEMM_SLICED_I8   2
+
+/* Workspace bytes ff_gemm needs for this shape and algorithm (0 for an
+ * invalid request or the FMA loop). */
+size_t ff_gemm_workspace_size(int64_t M, int64_t N, int64_t K, int32_t algo);
+
+ff_status ff_gemm(int64_t M, int64_t N, int64_t K, const float *A_hi,
+                  const float *A_lo, int64_t lda, const float *B_hi,
+                  const float *B_lo, int64_t ldb, float *C_hi, float *C_lo,
+                  int64_t ldc, int32_t algo, void *ws, size_t ws_bytes,
+                  void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Measurement probe                                                        */
 /* ------------------------------------------------------------------------ */
 

@@ -16,7 +16,8 @@ import ctypes
 
 import torch
 
-from ._lib import MATVEC_FAST, MATVEC_PLAIN, DotCfg, FFError, check, lib
+from ._lib import (GEMM_FMA_LOOP, GEMM_SLICED_BF16, GEMM_SLICED_I8, MATVEC_FAST, MATVEC_PLAIN,
+                   DotCfg, FFError, check, lib)
 
 __all__ = [
     "lib", "FFError", "DotCfg", "build_info",
@@ -24,6 +25,7 @@ __all__ = [
     "ff_dot_batched", "ff_dot_ff_batched", "ff_dot_batched_workspace_size",
     "ff_sum_batched", "ff_sum_ff_batched",
     "ff_matvec", "ff_matvec_backward", "ff_dot_backward", "MATVEC_FAST", "MATVEC_PLAIN",
+    "ff_gemm", "ff_gemm_workspace_size", "GEMM_FMA_LOOP", "GEMM_SLICED_BF16", "GEMM_SLICED_I8",
     "ff_empty", "ff_zeros",
 ]
 
@@ -331,3 +333,35 @@ def ff_dot_backward(g: torch.Tensor, x: torch.Tensor, y: torch.Tensor, want_dx: 
         check("ff_dot_backward", lib.ff_dot_backward(gh, gl, xh, xl, yh, yl, dxh, dxl, dyh, dyl, n,
                                                      _stream_handle(stream)))
     return dx, dy
+
+
+# ---------------------------------------------------------------------- GEMM
+
+def ff_gemm_workspace_size(M: int, N: int, K: int, algo: int = GEMM_SLICED_I8) -> int:
+    """Workspace bytes of ff_gemm for this shape and algorithm."""
+    return int(lib.ff_gemm_workspace_size(int(M), int(N), int(K), int(algo)))
+
+
+def ff_gemm(A: torch.Tensor, B: torch.Tensor, algo: int = GEMM_SLICED_I8, out=None,
+            workspace=None, stream=None) -> torch.Tensor:
+    """C = A B for float-float matrices A (2, M, K) and B (2, K, N)."""
+    M, K, lda = _check_matrix(A)
+    K2, N, ldb = _check_matrix(B)
+    if K2 != K:
+        raise ValueError(f"inner dimensions differ: {K} vs {K2}")
+    if A.device != B.device:
+        raise ValueError("A and B on different devices")
+    out = ff_empty((M, N), device=A.device) if out is None else out
+    _, _, ldc = _check_matrix(out)
+    if out.shape != (2, M, N):
+        raise ValueError(f"out must have shape (2, {M}, {N})")
+    nbytes = ff_gemm_workspace_size(M, N, K, algo)
+    ws = _workspace(nbytes, A.device, workspace)
+    Ah, Al = _planes(A)
+    Bh, Bl = _planes(B)
+    Ch, Cl = _planes(out)
+    with torch.cuda.device(A.device):
+        check("ff_gemm", lib.ff_gemm(M, N, K, Ah, Al, lda, Bh, Bl, ldb, Ch, Cl, ldc, int(algo),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                     _stream_handle(stream)))
+    return out

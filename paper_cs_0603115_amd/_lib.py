@@ -57,7 +57,14 @@ SIGNATURES = {
     "ff_matvec_backward": ([_i64, _i64, _P, _P, _i64, _P, _P, _P, _P, _P, _P, _i64, _P, _P, _i32,
                             _P, _sz, _P], _st),
     "ff_dot_backward": ([_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _i64, _P], _st),
+    "ff_gemm_workspace_size": ([_i64, _i64, _i64, _i32], _sz),
+    "ff_gemm": ([_i64, _i64, _i64, _P, _P, _i64, _P, _P, _i64, _P, _P, _i64, _i32, _P, _sz, _P],
+                _st),
 }
+
+GEMM_FMA_LOOP = 0
+GEMM_SLICED_BF16 = 1
+GEMM_SLICED_I8 = 2
 
 MATVEC_FAST = 0
 MATVEC_PLAIN = 1

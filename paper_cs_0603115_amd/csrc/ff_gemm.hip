@@ -1,0 +1,654 @@
+// ff_gemm.hip -- float-float matrix product C = A B (row-major planes).
+//
+// Two algorithms.
+//
+// FMA loop (the plain float-float GEMM): C_ij = Add22 accumulation, k
+// ascending, of Mul22(A_ik, B_kj) -- section 4.1's operators applied term by
+// term.  LDS-tiled (64 x 64 outputs per workgroup, 4 x 4 per thread), VALU
+// bound: ~26 binary32 operations per multiply-add, no contraction.  Bit for
+// bit the sequential definition.
+//
+// Sliced (the fast path; the paper has no GEMM): every entry of A and B is
+// turned into a signed fixed-point integer relative to a power of two of its
+// row (A) or column (B):
+//     X_ik = round(A_ik 2^(P - e_i)),  2^e_i > max_k |A_ik|,  P = 8S - 2,
+// and X is written as S = 7 signed 8-bit digits, X = sum_t d_t 256^(S-1-t).
+// A_ik B_kj then expands into digit products d_t d'_u of weight
+// 256^(2S-2-t-u); the pairs with t + u <= S - 1 (28 of 49) are kept.  Each
+// pair is an integer GEMM on matrix cores:
+//   * int8 digits, v_mfma_i32_32x32x32_i8, int32 accumulation;
+//   * BF16 digits (integers |d| <= 128 are exact in BF16),
+//     v_mfma_f32_32x32x16_bf16, FP32 accumulation moved into int32
+//     accumulators every 128 k, before any partial sum can exceed 2^24.
+// All partial sums are exact integers, so the hardware's accumulation order
+// does not matter.  Pairs on the same anti-diagonal D = t + u share one
+// accumulator (same weight): |S_D| <= 7 K 2^14 < 2^31 for K <= 16384 (longer
+// K is split into chunks summed with Add22).  The epilogue forms the exact
+// 128-bit integer T = sum_D S_D 256^(6-D) and rounds it once to float-float:
+//     C_ij ~ T 2^(e_i + f_j - 2P + 48).
+// No binary64 arithmetic is used anywhere.  Error sources: rounding of X (at
+// most one unit of 2^(e_i - P) per entry), the dropped pairs (< 2^-47 of
+// 2^(e_i + f_j) K), and the final rounding (2^-48 |C_ij|).
+//
+// Data layout of the digit planes (workspace): for each slice t and 64 x 64-
+// byte tile (64 rows of A, or 64 columns of B, by one K-stage of 64 bytes:
+// 64 int8 or 32 BF16 digits), the 4 KiB tile is contiguous; within a row the
+// four 16-byte chunks are permuted by chunk ^ ((row >> 1) & 3), so that the
+// matrix-core operand reads from LDS (8 rows x 16 bytes per LDS cycle) hit
+// distinct banks.  B is stored transposed (K contiguous per column).
+#include "ff_device.h"
+#include "ff_host.h"
+
+namespace ffk {
+
+// ----------------------------------------------------------------- plain
+
+constexpr int kPT = 64;   // plain tile: 64 x 64 outputs
+constexpr int kPK = 16;   // k per LDS stage
+
+__global__ __launch_bounds__(256) void gemm_fma_loop(int64_t M, int64_t N, int64_t K,
+                                                     const float *__restrict__ Ah,
+                                                     const float *__restrict__ Al, int64_t lda,
+                                                     const float *__restrict__ Bh,
+                                                     const float *__restrict__ Bl, int64_t ldb,
+                                                     float *__restrict__ Ch,
+                                                     float *__restrict__ Cl, int64_t ldc)
+{
+    __shared__ float sAh[kPK][kPT + 1], sAl[kPK][kPT + 1];
+    __shared__ float sBh[kPK][kPT], sBl[kPK][kPT];
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int64_t i0 = static_cast<int64_t>(blockIdx.y) * kPT;
+    const int64_t j0 = static_cast<int64_t>(blockIdx.x) * kPT;
+    float ch[4][4], cl[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            ch[r][c] = cl[r][c] = 0.0f;
+    for (int64_t k0 = 0; k0 < K; k0 += kPK) {
+        for (int e = threadIdx.x; e < kPT * kPK; e += 256) {
+            const int r = e / kPK, c = e % kPK;
+            const int64_t gi = i0 + r, gk = k0 + c;
+            const bool ok = gi < M && gk < K;
+            sAh[c][r] = ok ? Ah[gi * lda + gk] : 0.0f;
+            sAl[c][r] = ok ? Al[gi * lda + gk] : 0.0f;
+        }
+        for (int e = threadIdx.x; e < kPK * kPT; e += 256) {
+            const int r = e / kPT, c = e % kPT;
+            const int64_t gk = k0 + r, gj = j0 + c;
+            const bool ok = gk < K && gj < N;
+            sBh[r][c] = ok ? Bh[gk * ldb + gj] : 0.0f;
+            sBl[r][c] = ok ? Bl[gk * ldb + gj] : 0.0f;
+        }
+        __syncthreads();
+        const int kmax = (K - k0 < kPK) ? static_cast<int>(K - k0) : kPK;
+        for (int kk = 0; kk < kmax; ++kk) {
+            float ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                ah[r] = sAh[kk][ty + 16 * r];
+                al[r] = sAl[kk][ty + 16 * r];
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                bh[c] = sBh[kk][tx + 16 * c];
+                bl[c] = sBl[kk][tx + 16 * c];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    float ph, pl;
+                    ffd::mul22<false>(ah[r], al[r], bh[c], bl[c], ph, pl);
+                    ffd::add22(ch[r][c], cl[r][c], ph, pl, ch[r][c], cl[r][c]);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int64_t gi = i0 + ty + 16 * r, gj = j0 + tx + 16 * c;
+            if (gi < M && gj < N) {
+                Ch[gi * ldc + gj] = ch[r][c];
+                Cl[gi * ldc + gj] = cl[r][c];
+            }
+        }
+}
+
+// ---------------------------------------------------------------- sliced
+
+constexpr int kS = 7;                 // digits per operand
+constexpr int kP = 8 * kS - 2;        // fixed-point bits: |X| <= 2^kP
+constexpr int kTile = 64;             // rows (A) / columns (B) per tile
+constexpr int kTileBytes = 64 * 64;   // one slice tile: 64 rows x 64 bytes
+constexpr int kEpiShift = 8 * (kS - 1) - 2 * kP;   // C = T 2^(e + f + kEpiShift)
+constexpr int64_t kMaxKChunk = 16384; // int32 accumulators stay exact below this
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+struct DigitsI8 {
+    static constexpr int kEsize = 1;
+    static constexpr int kStageK = 64;        // digits per tile row per stage
+    static constexpr int kExtractStages = 0;  // int32 accumulation: never
+};
+struct DigitsBF16 {
+    static constexpr int kEsize = 2;
+    static constexpr int kStageK = 32;
+    static constexpr int kExtractStages = 4;  // 128 k per FP32 window
+};
+
+__device__ __forceinline__ uint32_t f32_bits(float v) { return __float_as_uint(v); }
+
+// Smallest e with |x| < 2^e for every x with |x| <= the value of bits ub.
+__device__ __forceinline__ int exponent_bound(uint32_t ub)
+{
+    if (ub == 0)
+        return 0;
+    const int be = static_cast<int>(ub >> 23);
+    return be == 0 ? -126 : be - 126;
+}
+
+// round(v * 2^scale_exp) as an integer (ties away from zero), saturating
+// far outside the digit range.
+__device__ __forceinline__ int64_t fixed_round(float v, int scale_exp)
+{
+    const uint32_t b = f32_bits(v);
+    int be = static_cast<int>((b >> 23) & 255u);
+    int64_t mant = b & 0x7fffffu;
+    if (be == 0) {
+        if (mant == 0)
+            return 0;
+        be = 1;
+    } else {
+        mant |= 0x800000;
+    }
+    const int sh = be - 150 + scale_exp;      // v = mant * 2^(be - 150)
+    int64_t m;
+    if (sh >= 0)
+        m = mant << (sh < 38 ? sh : 38);
+    else if (sh > -40)
+        m = (mant + (int64_t(1) << (-sh - 1))) >> (-sh);
+    else
+        m = 0;
+    return (b >> 31) ? -m : m;
+}
+
+// Digits of one float-float entry: d[0] most significant.
+__device__ __forceinline__ void entry_digits(float hi, float lo, int e, int d[kS])
+{
+    const int se = kP - e;
+    int64_t X = fixed_round(hi, se) + fixed_round(lo, se);
+    const int64_t lim = int64_t(127) << (8 * (kS - 1));
+    X = X > lim ? lim : (X < -lim ? -lim : X);
+#pragma unroll
+    for (int t = kS - 1; t >= 0; --t) {
+        const int64_t dt = ((X + 128) & 255) - 128;
+        d[t] = static_cast<int>(dt);
+        X = (X - dt) >> 8;
+    }
+}
+
+template <class Dg>
+__device__ __forceinline__ void put_digit(uint8_t *chunk, int q, int d)
+{
+    if constexpr (Dg::kEsize == 1) {
+        chunk[q] = static_cast<uint8_t>(static_cast<int8_t>(d));
+    } else {
+        // |d| <= 128 has at most 8 significant bits: the BF16 pattern is the
+        // upper half of the binary32 pattern, exactly.
+        const uint16_t bf = static_cast<uint16_t>(f32_bits(static_cast<float>(d)) >> 16);
+        reinterpret_cast<uint16_t *>(chunk)[q] = bf;
+    }
+}
+
+__device__ __forceinline__ int64_t tile_offset(int t, int bi, int bk, int nB, int nBK, int row,
+                                               int chunk)
+{
+    return ((static_cast<int64_t>(t) * nB + bi) * nBK + bk) * kTileBytes + row * 64 +
+           ((chunk ^ ((row >> 1) & 3)) * 16);
+}
+
+__global__ __launch_bounds__(256) void fill_u32(uint32_t *p, int64_t n)
+{
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * 256)
+        p[i] = 0u;
+}
+
+// rowmax[i] = max_k |A_hi[i, k]| (as bits).  One wavefront per (row, 4096-k
+// segment); integer atomicMax, so the result does not depend on order.
+__global__ __launch_bounds__(256) void absmax_rows(int64_t M, int64_t K,
+                                                   const float *__restrict__ Ah, int64_t lda,
+                                                   uint32_t *__restrict__ rowmax)
+{
+    const int64_t row = static_cast<int64_t>(blockIdx.y) * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= M)
+        return;
+    const int64_t k0 = static_cast<int64_t>(blockIdx.x) * 4096;
+    const int64_t k1 = (k0 + 4096 < K) ? k0 + 4096 : K;
+    uint32_t m = 0;
+    for (int64_t k = k0 + lane; k < k1; k += 64)
+        m = max(m, f32_bits(Ah[row * lda + k]) & 0x7fffffffu);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        m = max(m, static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), off, 64)));
+    if (lane == 0 && m)
+        atomicMax(&rowmax[row], m);
+}
+
+// colmax[j] = max_k |B_hi[k, j]|: thread per column, 256-row bands.
+__global__ __launch_bounds__(256) void absmax_cols(int64_t K, int64_t N,
+                                                   const float *__restrict__ Bh, int64_t ldb,
+                                                   uint32_t *__restrict__ colmax)
+{
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (j >= N)
+        return;
+    const int64_t k0 = static_cast<int64_t>(blockIdx.y) * 256;
+    const int64_t k1 = (k0 + 256 < K) ? k0 + 256 : K;
+    uint32_t m = 0;
+    for (int64_t k = k0; k < k1; ++k)
+        m = max(m, f32_bits(Bh[k * ldb + j]) & 0x7fffffffu);
+    if (m)
+        atomicMax(&colmax[j], m);
+}
+
+// A digit planes: one workgroup per (64-row tile, K stage); thread = one
+// 16-byte chunk of one row, all S slices.
+template <class Dg>
+__global__ __launch_bounds__(256) void slice_rows(int64_t M, int64_t K,
+                                                  const float *__restrict__ Ah,
+                                                  const float *__restrict__ Al, int64_t lda,
+                                                  const uint32_t *__restrict__ rowmax, int nBI,
+                                                  int nBK, uint8_t *__restrict__ planes)
+{
+    constexpr int kPerChunk = 16 / Dg::kEsize;
+    const int bk = blockIdx.x, bi = blockIdx.y;
+    const int row = threadIdx.x >> 2, chunk = threadIdx.x & 3;
+    const int64_t i = static_cast<int64_t>(bi) * kTile + row;
+    const int64_t kb = static_cast<int64_t>(bk) * Dg::kStageK + chunk * kPerChunk;
+    alignas(16) uint8_t out[kS][16];
+    const int e = i < M ? exponent_bound(rowmax[i]) : 0;
+#pragma unroll
+    for (int q = 0; q < kPerChunk; ++q) {
+        const int64_t k = kb + q;
+        int d[kS];
+        if (i < M && k < K)
+            entry_digits(Ah[i * lda + k], Al[i * lda + k], e, d);
+        else
+#pragma unroll
+            for (int t = 0; t < kS; ++t)
+                d[t] = 0;
+#pragma unroll
+        for (int t = 0; t < kS; ++t)
+            put_digit<Dg>(out[t], q, d[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < kS; ++t)
+        *reinterpret_cast<uint4 *>(planes + tile_offset(t, bi, bk, nBI, nBK, row, chunk)) =
+            *reinterpret_cast<const uint4 *>(out[t]);
+}
+
+// B^T digit planes: one workgroup per (64-column tile, K stage); lanes take
+// consecutive columns (coalesced reads of B's rows).
+template <class Dg>
+__global__ __launch_bounds__(256) void slice_cols(int64_t K, int64_t N,
+                                                  const float *__restrict__ Bh,
+                                                  const float *__restrict__ Bl, int64_t ldb,
+                                                  const uint32_t *__restrict__ colmax, int nBJ,
+                                                  int nBK, uint8_t *__restrict__ planes)
+{
+    constexpr int kPerChunk = 16 / Dg::kEsize;
+    const int bk = blockIdx.x, bj = blockIdx.y;
+    const int col = threadIdx.x & 63, chunk = threadIdx.x >> 6;
+    const int64_t j = static_cast<int64_t>(bj) * kTile + col;
+    const int64_t kb = static_cast<int64_t>(bk) * Dg::kStageK + chunk * kPerChunk;
+    alignas(16) uint8_t out[kS][16];
+    const int e = j < N ? exponent_bound(colmax[j]) : 0;
+#pragma unroll
+    for (int q = 0; q < kPerChunk; ++q) {
+        const int64_t k = kb + q;
+        int d[kS];
+        if (j < N && k < K)
+            entry_digits(Bh[k * ldb + j], Bl[k * ldb + j], e, d);
+        else
+#pragma unroll
+            for (int t = 0; t < kS; ++t)
+                d[t] = 0;
+#pragma unroll
+        for (int t = 0; t < kS; ++t)
+            put_digit<Dg>(out[t], q, d[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < kS; ++t)
+        *reinterpret_cast<uint4 *>(planes + tile_offset(t, bj, bk, nBJ, nBK, col, chunk)) =
+            *reinterpret_cast<const uint4 *>(out[t]);
+}
+
+// Round the integer t to 24 bits, nearest-even: t ~ mant 2^E (E >= 0).
+__device__ __forceinline__ void round_i128(__int128 t, int &neg, uint32_t &mant, int &E)
+{
+    neg = t < 0;
+    const unsigned __int128 u = neg ? static_cast<unsigned __int128>(-t)
+                                    : static_cast<unsigned __int128>(t);
+    const uint64_t hi = static_cast<uint64_t>(u >> 64), lo = static_cast<uint64_t>(u);
+    const int nbits = hi ? 128 - __builtin_clzll(hi) : (lo ? 64 - __builtin_clzll(lo) : 0);
+    if (nbits <= 24) {
+        mant = static_cast<uint32_t>(lo);
+        E = 0;
+        return;
+    }
+    int sh = nbits - 24;
+    unsigned __int128 m = u >> sh;
+    const unsigned __int128 rem = u - (m << sh);
+    const unsigned __int128 half = static_cast<unsigned __int128>(1) << (sh - 1);
+    if (rem > half || (rem == half && (m & 1))) {
+        m += 1;
+        if (m >> 24) {
+            m >>= 1;
+            sh += 1;
+        }
+    }
+    mant = static_cast<uint32_t>(m);
+    E = sh;
+}
+
+// (hi, lo) = (RN(T), RN(T - RN(T))) * 2^scale.
+__device__ __forceinline__ void i128_to_ff(__int128 T, int scale, float &hi, float &lo)
+{
+    int neg, E;
+    uint32_t mant;
+    round_i128(T, neg, mant, E);
+    const __int128 top = static_cast<__int128>(mant) << E;
+    const __int128 rem = T - (neg ? -top : top);
+    const float h = __builtin_ldexpf(static_cast<float>(mant), E + scale);
+    hi = neg ? -h : h;
+    int rneg, rE;
+    uint32_t rmant;
+    round_i128(rem, rneg, rmant, rE);
+    const float l = __builtin_ldexpf(static_cast<float>(rmant), rE + scale);
+    lo = rneg ? -l : l;
+}
+
+__device__ __forceinline__ i32x16 mma(const uint4 &a, const uint4 &b, const i32x16 &c, DigitsI8)
+{
+    return __builtin_amdgcn_mfma_i32_32x32x32_i8(*reinterpret_cast<const i32x4 *>(&a),
+                                                 *reinterpret_cast<const i32x4 *>(&b), c, 0, 0,
+                                                 0);
+}
+__device__ __forceinline__ f32x16 mma(const uint4 &a, const uint4 &b, const f32x16 &c,
+                                      DigitsBF16)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const bf16x8 *>(&a),
+                                                   *reinterpret_cast<const bf16x8 *>(&b), c, 0,
+                                                   0, 0);
+}
+
+template <class Dg> struct AccOf;
+template <> struct AccOf<DigitsI8> { using T = i32x16; };
+template <> struct AccOf<DigitsBF16> { using T = f32x16; };
+
+// The sliced product.  Workgroup = 4 wavefronts = 64 x 64 outputs; wavefront
+// (wm, wn) owns a 32 x 32 block held as S diagonal accumulators of one
+// 32x32 matrix-core tile each.  K-stages [bk0, bk1) are streamed through
+// double-buffered LDS (all S slices of the A and B tiles per stage).
+template <class Dg>
+__global__ __launch_bounds__(256) void gemm_sliced(int64_t M, int64_t N, int nBI, int nBJ,
+                                                   int nBK, int bk0, int bk1,
+                                                   const uint8_t *__restrict__ Ap,
+                                                   const uint8_t *__restrict__ Bp,
+                                                   const uint32_t *__restrict__ rowmax,
+                                                   const uint32_t *__restrict__ colmax,
+                                                   float *__restrict__ Ch,
+                                                   float *__restrict__ Cl, int64_t ldc,
+                                                   int accumulate)
+{
+    using Acc = typename AccOf<Dg>::T;
+    __shared__ uint4 lds_raw[2 * 2 * kS * kTileBytes / 16];   // 112 KiB
+    uint8_t *lds = reinterpret_cast<uint8_t *>(lds_raw);
+    // lds[buf][op][slice][4096]
+    auto tile_at = [&](int buf, int op, int t) {
+        return lds + ((buf * 2 + op) * kS + t) * kTileBytes;
+    };
+    const int bj = blockIdx.x, bi = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+
+    Acc acc[kS];
+    i32x16 iacc[kS];
+#pragma unroll
+    for (int d = 0; d < kS; ++d) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            acc[d][r] = 0;
+            iacc[d][r] = 0;
+        }
+    }
+
+    uint4 stage_a[kS], stage_b[kS];
+    auto fetch = [&](int bk) {
+#pragma unroll
+        for (int t = 0; t < kS; ++t) {
+            stage_a[t] = reinterpret_cast<const uint4 *>(
+                Ap + ((static_cast<int64_t>(t) * nBI + bi) * nBK + bk) * kTileBytes)[tid];
+            stage_b[t] = reinterpret_cast<const uint4 *>(
+                Bp + ((static_cast<int64_t>(t) * nBJ + bj) * nBK + bk) * kTileBytes)[tid];
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int t = 0; t < kS; ++t) {
+            reinterpret_cast<uint4 *>(tile_at(buf, 0, t))[tid] = stage_a[t];
+            reinterpret_cast<uint4 *>(tile_at(buf, 1, t))[tid] = stage_b[t];
+        }
+    };
+
+    const int ra = wm * 32 + (lane & 31);   // A tile row of this lane
+    const int rb = wn * 32 + (lane & 31);   // B tile row (= C column) of this lane
+    if (bk0 < bk1) {
+        fetch(bk0);
+        stash(0);
+    }
+    __syncthreads();
+    for (int bk = bk0; bk < bk1; ++bk) {
+        const int buf = (bk - bk0) & 1;
+        if (bk + 1 < bk1)
+            fetch(bk + 1);
+#pragma unroll
+        for (int step = 0; step < 2; ++step) {
+            const int chunk = 2 * step + (lane >> 5);
+            const int oa = ra * 64 + ((chunk ^ ((ra >> 1) & 3)) * 16);
+            const int ob = rb * 64 + ((chunk ^ ((rb >> 1) & 3)) * 16);
+            uint4 fa[kS], fb[kS];
+#pragma unroll
+            for (int t = 0; t < kS; ++t) {
+                fa[t] = *reinterpret_cast<const uint4 *>(tile_at(buf, 0, t) + oa);
+                fb[t] = *reinterpret_cast<const uint4 *>(tile_at(buf, 1, t) + ob);
+            }
+#pragma unroll
+            for (int d = 0; d < kS; ++d)
+#pragma unroll
+                for (int t = 0; t <= d; ++t)
+                    acc[d] = mma(fa[t], fb[d - t], acc[d], Dg{});
+        }
+        if constexpr (Dg::kExtractStages > 0) {
+            if ((bk - bk0 + 1) % Dg::kExtractStages == 0 || bk + 1 == bk1) {
+#pragma unroll
+                for (int d = 0; d < kS; ++d)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        iacc[d][r] += static_cast<int>(acc[d][r]);
+                        acc[d][r] = 0.0f;
+                    }
+            }
+        }
+        if (bk + 1 < bk1)
+            stash(buf ^ 1);
+        __syncthreads();
+    }
+
+    // Epilogue: lane holds C[8*(r/4) + 4*(lane/32) + (r%4)][lane%32] of the
+    // wavefront's 32x32 block for r = 0..15.
+    const int64_t j = static_cast<int64_t>(bj) * kTile + wn * 32 + (lane & 31);
+    const int fj = j < N ? exponent_bound(colmax[j]) : 0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t i = static_cast<int64_t>(bi) * kTile + wm * 32 + m;
+        if (i >= M || j >= N)
+            continue;
+        __int128 T = 0;
+#pragma unroll
+        for (int d = 0; d < kS; ++d) {
+            int s;
+            if constexpr (Dg::kExtractStages > 0)
+                s = iacc[d][r];
+            else
+                s = acc[d][r];
+            T = (T << 8) + static_cast<__int128>(s);
+        }
+        float h, l;
+        i128_to_ff(T, exponent_bound(rowmax[i]) + fj + kEpiShift, h, l);
+        if (accumulate)
+            ffd::add22(Ch[i * ldc + j], Cl[i * ldc + j], h, l, h, l);
+        Ch[i * ldc + j] = h;
+        Cl[i * ldc + j] = l;
+    }
+}
+
+struct SliceGeom {
+    int nBI, nBJ, nBK;
+    size_t plane_a, plane_b;   // bytes of all A / B digit planes
+    size_t off_rowmax, off_colmax, off_a, off_b, total;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+inline SliceGeom slice_geom(int64_t M, int64_t N, int64_t K, int esize, int stage_k)
+{
+    SliceGeom g;
+    g.nBI = static_cast<int>((M + kTile - 1) / kTile);
+    g.nBJ = static_cast<int>((N + kTile - 1) / kTile);
+    g.nBK = static_cast<int>((K + stage_k - 1) / stage_k);
+    g.plane_a = static_cast<size_t>(kS) * g.nBI * g.nBK * kTileBytes;
+    g.plane_b = static_cast<size_t>(kS) * g.nBJ * g.nBK * kTileBytes;
+    g.off_rowmax = 0;
+    g.off_colmax = align256(sizeof(uint32_t) * M);
+    g.off_a = g.off_colmax + align256(sizeof(uint32_t) * N);
+    g.off_b = g.off_a + align256(g.plane_a);
+    g.total = g.off_b + align256(g.plane_b);
+    (void)esize;
+    return g;
+}
+
+template <class Dg>
+ff_status sliced_gemm(int64_t M, int64_t N, int64_t K, const float *Ah, const float *Al,
+                      int64_t lda, const float *Bh, const float *Bl, int64_t ldb, float *Ch,
+                      float *Cl, int64_t ldc, void *ws, size_t ws_bytes, hipStream_t st)
+{
+    const SliceGeom g = slice_geom(M, N, K, Dg::kEsize, Dg::kStageK);
+    if (!ws)
+        return FF_ERR_NULL;
+    if (ws_bytes < g.total)
+        return FF_ERR_WORKSPACE;
+    if (!ffh::aligned(ws, 256))
+        return FF_ERR_ALIGN;
+    if (g.nBI > 65535 || g.nBJ > 65535 || ffh::cdiv(M, 4) > 65535 || ffh::cdiv(K, 256) > 65535)
+        return FF_ERR_SIZE;
+    char *base = static_cast<char *>(ws);
+    uint32_t *rowmax = reinterpret_cast<uint32_t *>(base + g.off_rowmax);
+    uint32_t *colmax = reinterpret_cast<uint32_t *>(base + g.off_colmax);
+    uint8_t *Ap = reinterpret_cast<uint8_t *>(base + g.off_a);
+    uint8_t *Bp = reinterpret_cast<uint8_t *>(base + g.off_b);
+
+    const int64_t nfill = static_cast<int64_t>((g.off_a) / sizeof(uint32_t));
+    hipLaunchKernelGGL(fill_u32, dim3(static_cast<unsigned>(ffh::cdiv(nfill, 256) < 4096 ? ffh::cdiv(nfill, 256) : 4096)),
+                       dim3(256), 0, st, rowmax, nfill);
+    if (K > 0) {
+        hipLaunchKernelGGL(absmax_rows,
+                           dim3(static_cast<unsigned>(ffh::cdiv(K, 4096)),
+                                static_cast<unsigned>(ffh::cdiv(M, 4))),
+                           dim3(256), 0, st, M, K, Ah, lda, rowmax);
+        hipLaunchKernelGGL(absmax_cols,
+                           dim3(static_cast<unsigned>(ffh::cdiv(N, 256)),
+                                static_cast<unsigned>(ffh::cdiv(K, 256))),
+                           dim3(256), 0, st, K, N, Bh, ldb, colmax);
+        hipLaunchKernelGGL((slice_rows<Dg>), dim3(g.nBK, g.nBI), dim3(256), 0, st, M, K, Ah, Al,
+                           lda, rowmax, g.nBI, g.nBK, Ap);
+        hipLaunchKernelGGL((slice_cols<Dg>), dim3(g.nBK, g.nBJ), dim3(256), 0, st, K, N, Bh, Bl,
+                           ldb, colmax, g.nBJ, g.nBK, Bp);
+    }
+    const int stages_per_chunk = static_cast<int>(kMaxKChunk / Dg::kStageK);
+    int bk0 = 0;
+    do {
+        const int bk1 = (bk0 + stages_per_chunk < g.nBK) ? bk0 + stages_per_chunk : g.nBK;
+        hipLaunchKernelGGL((gemm_sliced<Dg>), dim3(g.nBJ, g.nBI), dim3(256), 0, st, M, N,
+                           g.nBI, g.nBJ, g.nBK, bk0, bk1, Ap, Bp, rowmax, colmax, Ch, Cl, ldc,
+                           bk0 > 0 ? 1 : 0);
+        bk0 = bk1;
+    } while (bk0 < g.nBK);
+    return ffh::launch_status();
+}
+
+} // namespace ffk
+
+using namespace ffk;
+
+extern "C" {
+
+size_t ff_gemm_workspace_size(int64_t M, int64_t N, int64_t K, int32_t algo)
+{
+    if (M < 0 || N < 0 || K < 0)
+        return 0;
+    switch (algo) {
+    case FF_GEMM_FMA_LOOP: return 0;
+    case FF_GEMM_SLICED_BF16: return slice_geom(M, N, K, 2, DigitsBF16::kStageK).total;
+    case FF_GEMM_SLICED_I8: return slice_geom(M, N, K, 1, DigitsI8::kStageK).total;
+    default: return 0;
+    }
+}
+
+ff_status ff_gemm(int64_t M, int64_t N, int64_t K, const float *A_hi, const float *A_lo,
+                  int64_t lda, const float *B_hi, const float *B_lo, int64_t ldb, float *C_hi,
+                  float *C_lo, int64_t ldc, int32_t algo, void *ws, size_t ws_bytes, void *stream)
+{
+    if (M < 0 || N < 0 || K < 0 || lda < K || ldb < N || ldc < N)
+        return FF_ERR_SIZE;
+    if (algo != FF_GEMM_FMA_LOOP && algo != FF_GEMM_SLICED_BF16 && algo != FF_GEMM_SLICED_I8)
+        return FF_ERR_ARG;
+    if (M == 0 || N == 0)
+        return FF_OK;
+    if (!C_hi || !C_lo || (K > 0 && (!A_hi || !A_lo || !B_hi || !B_lo)))
+        return FF_ERR_NULL;
+    for (const void *p : {static_cast<const void *>(A_hi), static_cast<const void *>(A_lo),
+                          static_cast<const void *>(B_hi), static_cast<const void *>(B_lo),
+                          static_cast<const void *>(C_hi), static_cast<const void *>(C_lo)})
+        if (!ffh::aligned(p, 4))
+            return FF_ERR_ALIGN;
+    if (ffh::cdiv(M, 64) > 65535 || ffh::cdiv(N, 64) > INT32_MAX)
+        return FF_ERR_SIZE;
+    hipStream_t st = ffh::as_stream(stream);
+    switch (algo) {
+    case FF_GEMM_FMA_LOOP:
+        hipLaunchKernelGGL(gemm_fma_loop,
+                           dim3(static_cast<unsigned>(ffh::cdiv(N, kPT)),
+                                static_cast<unsigned>(ffh::cdiv(M, kPT))),
+                           dim3(256), 0, st, M, N, K, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, C_lo,
+                           ldc);
+        return ffh::launch_status();
+    case FF_GEMM_SLICED_BF16:
+        return sliced_gemm<DigitsBF16>(M, N, K, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, C_lo, ldc,
+                                       ws, ws_bytes, st);
+    default:
+        return sliced_gemm<DigitsI8>(M, N, K, A_hi, A_lo, lda, B_hi, B_lo, ldb, C_hi, C_lo, ldc,
+                                     ws, ws_bytes, st);
+    }
+}
+
+} // extern "C"

@@ -202,3 +202,27 @@ def test_sum_and_autotune_validation():
                                           ctypes.byref(ms)) == ERR_ARG
     assert ff.lib.ff_dot_batched_autotune(4096, 8192, 12288, 4, 100, 1 << 20, 1 << 16, 1 << 21,
                                           1 << 22, 3, None, None, ctypes.byref(ms)) == ERR_NULL
+
+
+def test_gemm_validation_and_workspace():
+    g = ff.lib.ff_gemm
+    size = ff.lib.ff_gemm_workspace_size
+    assert size(64, 64, 64, 0) == 0                       # FMA loop needs none
+    w8, w16 = size(100, 70, 333, 2), size(100, 70, 333, 1)
+    assert w8 > 0 and w16 > w8
+    # digit planes: 7 slices x 64-row tiles x 64-byte stages
+    assert w8 >= 7 * (128 + 128) * 384
+    assert size(-1, 4, 4, 2) == 0 and size(4, 4, 4, 9) == 0
+    P = [4096 * (k + 1) for k in range(6)]
+    ws = 1 << 24
+    assert g(-1, 4, 4, P[0], P[1], 4, P[2], P[3], 4, P[4], P[5], 4, 0, None, 0, None) == ERR_SIZE
+    assert g(4, 4, 4, P[0], P[1], 3, P[2], P[3], 4, P[4], P[5], 4, 0, None, 0, None) == ERR_SIZE
+    assert g(4, 4, 4, P[0], P[1], 4, P[2], P[3], 4, P[4], P[5], 3, 0, None, 0, None) == ERR_SIZE
+    assert g(4, 4, 4, P[0], P[1], 4, P[2], P[3], 4, P[4], P[5], 4, 7, None, 0, None) == ERR_ARG
+    assert g(0, 4, 4, P[0], P[1], 4, P[2], P[3], 4, P[4], P[5], 4, 2, None, 0, None) == 0
+    assert g(4, 4, 4, None, P[1], 4, P[2], P[3], 4, P[4], P[5], 4, 0, None, 0, None) == ERR_NULL
+    assert g(4, 4, 4, P[0], P[1], 4, P[2], P[3] + 1, 4, P[4], P[5], 4, 0, None, 0, None) == ERR_ALIGN
+    need = size(4, 4, 4, 2)
+    assert g(4, 4, 4, *P[:2], 4, *P[2:4], 4, *P[4:], 4, 2, None, need, None) == ERR_NULL
+    assert g(4, 4, 4, *P[:2], 4, *P[2:4], 4, *P[4:], 4, 2, ws, need - 1, None) == ERR_WS
+    assert g(4, 4, 4, *P[:2], 4, *P[2:4], 4, *P[4:], 4, 2, ws + 16, need, None) == ERR_ALIGN

@@ -1,0 +1,179 @@
+"""GPU parity of the float-float GEMM.
+
+* FMA loop: bit-exact against the oracle's plain float-float GEMM (Add22
+  accumulation of Mul22 terms, k ascending).
+* Sliced (int8 and BF16 digits on matrix cores): against the exact product
+  (long accumulator) entry by entry, normwise |C - exact| <= 2^-44 (|A||B|);
+  exactly equal to each other (both sum the same digit products exactly);
+  exact on integer data and on A times the identity when every row of A sits
+  in one binade.
+"""
+import math
+import sys
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+import ff_inputs as fi
+import oracle
+from fpexact import frac, same_bits
+
+pytestmark = pytest.mark.gpu
+
+TWO_M44 = Fraction(1, 1 << 44)
+
+
+def _ff():
+    import paper_cs_0603115_amd as ff
+    return ff
+
+
+def _announce(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def check_entries(A, B, C, rows, cols, label, target=TWO_M44):
+    """C at (rows x cols) against the exact product, normwise."""
+    An, Bn, Cn = A.cpu().numpy(), B.cpu().numpy(), C.cpu().numpy()
+    ri, ci = np.meshgrid(np.asarray(rows), np.asarray(cols), indexing="ij")
+    ri, ci = ri.ravel(), ci.ravel()
+    exact = oracle.exact_gemm_entries(An[0], An[1], Bn[0], Bn[1], ri, ci)
+    scale = oracle.exact_absgemm_entries(An[0], An[1], Bn[0], Bn[1], ri, ci)
+    worst = -math.inf
+    for t, (i, j) in enumerate(zip(ri, ci)):
+        err = abs(frac(Cn[0, i, j]) + frac(Cn[1, i, j]) - exact[t])
+        if scale[t] == 0:
+            assert err == 0, (label, i, j)
+            continue
+        assert err <= target * scale[t], (label, i, j, float(err / scale[t]))
+        if err:
+            worst = max(worst, math.log2(err / scale[t]))
+    return worst
+
+
+ALGOS = ["i8", "bf16"]
+
+
+def _algo(name):
+    ff = _ff()
+    return {"i8": ff.GEMM_SLICED_I8, "bf16": ff.GEMM_SLICED_BF16, "fma": ff.GEMM_FMA_LOOP}[name]
+
+
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (5, 3, 7), (64, 64, 64), (100, 70, 333),
+                                   (130, 257, 200), (33, 65, 1000)])
+def test_fma_loop_is_bitexact(M, N, K):
+    ff = _ff()
+    A = fi.gaussian_ff((M, K), 11 + M)
+    B = fi.gaussian_ff((K, N), 12 + N)
+    C = ff.ff_gemm(A.cuda(), B.cuda(), algo=ff.GEMM_FMA_LOOP).cpu().numpy()
+    Ch, Cl = oracle.gemm_ff_seq(A[0].numpy(), A[1].numpy(), B[0].numpy(), B[1].numpy())
+    assert same_bits(C[0], Ch) and same_bits(C[1], Cl)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (5, 3, 7), (64, 64, 64), (100, 70, 333),
+                                   (130, 257, 200), (33, 65, 1000)])
+def test_sliced_against_exact(algo, M, N, K):
+    ff = _ff()
+    A = fi.gaussian_ff((M, K), 21 + M).cuda()
+    B = fi.gaussian_ff((K, N), 22 + N).cuda()
+    C = ff.ff_gemm(A, B, algo=_algo(algo))
+    check_entries(A, B, C, range(M), range(N), f"{algo} {M}x{N}x{K}")
+
+
+def test_sliced_int8_and_bf16_agree_bitwise():
+    ff = _ff()
+    A = fi.gaussian_ff((200, 700), 31).cuda()
+    B = fi.gaussian_ff((700, 150), 32).cuda()
+    C8 = ff.ff_gemm(A, B, algo=ff.GEMM_SLICED_I8)
+    C16 = ff.ff_gemm(A, B, algo=ff.GEMM_SLICED_BF16)
+    again = ff.ff_gemm(A, B, algo=ff.GEMM_SLICED_I8)
+    assert torch.equal(C8.view(torch.int32), C16.view(torch.int32))
+    assert torch.equal(C8.view(torch.int32), again.view(torch.int32))
+
+
+@pytest.mark.parametrize("algo", ALGOS + ["fma"])
+def test_integer_matrices_are_exact(algo):
+    ff = _ff()
+    rng = np.random.default_rng(41)
+    Ai = rng.integers(-3000, 3000, (96, 300))
+    Bi = rng.integers(-3000, 3000, (300, 80))
+    A = torch.stack([torch.from_numpy(Ai.astype(np.float32)), torch.zeros(96, 300)]).cuda()
+    B = torch.stack([torch.from_numpy(Bi.astype(np.float32)), torch.zeros(300, 80)]).cuda()
+    C = ff.ff_gemm(A, B, algo=_algo(algo)).cpu().numpy()
+    want = Ai @ Bi
+    got = C[0].astype(np.int64) + C[1].astype(np.int64)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_identity_reproduces_single_binade_rows(algo):
+    # rows of A inside one binade: the 54-bit fixed point holds every entry's
+    # 48 significant bits, and B = I keeps one digit-pair column per entry
+    ff = _ff()
+    M, K = 70, 96
+    mant = fi.random_ff(M * K, 51, 0, 0, max_gap=5).reshape(2, M, K).abs()   # hi in [1, 2)
+    lo_sign = torch.sign(fi.random_ff(M * K, 52, 0, 0)[1]).reshape(M, K)
+    mant[1] *= lo_sign
+    scale = torch.exp2(torch.randint(-20, 20, (M, 1)).float())
+    A = (mant * scale).cuda()
+    B = torch.stack([torch.eye(K), torch.zeros(K, K)]).cuda()
+    C = ff.ff_gemm(A, B, algo=_algo(algo))
+    assert torch.equal(C.view(torch.int32), A.view(torch.int32))
+
+
+def test_long_k_is_split_into_exact_chunks():
+    ff = _ff()
+    M, N, K = 64, 48, 16384 + 96
+    A = fi.gaussian_ff((M, K), 61).cuda()
+    B = fi.gaussian_ff((K, N), 62).cuda()
+    for algo in ALGOS:
+        C = ff.ff_gemm(A, B, algo=_algo(algo))
+        check_entries(A, B, C, range(0, M, 7), range(0, N, 5), f"{algo} long K")
+
+
+def test_zero_k_gives_zero():
+    ff = _ff()
+    A = torch.zeros(2, 5, 0, device="cuda")
+    B = torch.zeros(2, 0, 6, device="cuda")
+    for algo in ALGOS + ["fma"]:
+        C = ff.ff_gemm(A, B, algo=_algo(algo))
+        torch.cuda.synchronize()
+        assert C.shape == (2, 5, 6) and torch.count_nonzero(C) == 0
+
+
+def test_full_size_4096():
+    # C = A B, M = N = K = 4096, entries normal(0,1) split into float-float:
+    # 16 seeded 64 x 64 blocks (corners included) against the exact product,
+    # the FMA loop bit-exact on one block.
+    ff = _ff()
+    n = 4096
+    _announce("[gpu] gemm 4096^3: generating")
+    A = fi.gaussian_ff((n, n), 115004, device="cuda")
+    B = fi.gaussian_ff((n, n), 115014, device="cuda")
+    _announce("[gpu] gemm 4096^3: sliced int8 and bf16")
+    C8 = ff.ff_gemm(A, B, algo=ff.GEMM_SLICED_I8)
+    C16 = ff.ff_gemm(A, B, algo=ff.GEMM_SLICED_BF16)
+    torch.cuda.synchronize()
+    assert torch.equal(C8.view(torch.int32), C16.view(torch.int32))
+    rng = np.random.default_rng(115004)
+    starts = [(0, 0), (0, n - 64), (n - 64, 0), (n - 64, n - 64)]
+    starts += [tuple(int(v) for v in rng.integers(0, n - 64, 2)) for _ in range(12)]
+    worst = -math.inf
+    for bi, (r0, c0) in enumerate(starts):
+        _announce(f"  block {bi} at ({r0}, {c0})")
+        w = check_entries(A, B, C8, range(r0, r0 + 64), range(c0, c0 + 64), f"block {r0},{c0}")
+        worst = max(worst, w)
+    _announce(f"  sliced worst normwise log2 error {worst:.2f}")
+    _announce("[gpu] gemm 4096^3: FMA loop, one block bit-exact")
+    Cp = ff.ff_gemm(A, B, algo=ff.GEMM_FMA_LOOP)
+    torch.cuda.synchronize()
+    r0, c0 = starts[5]
+    An, Bn = A.cpu().numpy(), B.cpu().numpy()
+    Ch, Cl = oracle.gemm_ff_seq(An[0], An[1], Bn[0], Bn[1], rows=(r0, r0 + 64), cols=(c0, c0 + 64))
+    Cpn = Cp[:, r0:r0 + 64, c0:c0 + 64].cpu().numpy()
+    assert same_bits(Cpn[0], Ch) and same_bits(Cpn[1], Cl)
+    del A, B, C8, C16, Cp
+    torch.cuda.empty_cache()
