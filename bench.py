@@ -31,8 +31,44 @@ BYTES_PER_FF_OP = 24           # 4 binary32 words in, 2 out
 OPS = ["add", "sub", "mul", "div"]
 
 
+PROFILE_SUMMARY = os.path.join(_ROOT, "profiles", "elementwise_ff_ops_2p28.md")
+
+
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
+
+
+def profiled_traffic(op: str, n: int):
+    """HBM bytes per launch of ff_<op> measured by rocprofv3 (FETCH_SIZE and
+    WRITE_SIZE, calibrated on the copy probe) and recorded in the profile
+    summary -- or None if that summary is missing, was taken at another size,
+    or the kernel sources changed since (sha256 of the listed files)."""
+    import hashlib
+
+    try:
+        text = open(PROFILE_SUMMARY).read()
+    except OSError:
+        return None
+    if n != 1 << 28:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        parts = line.split()
+        if len(parts) >= 2 and parts[0] in ("traffic_bytes_per_launch", "sources_sha256", "sources"):
+            fields.setdefault(parts[0], []).append(parts[1:])
+    try:
+        digest = hashlib.sha256()
+        for path in fields["sources"][0]:
+            with open(os.path.join(_ROOT, path), "rb") as f:
+                digest.update(f.read())
+        if digest.hexdigest() != fields["sources_sha256"][0][0]:
+            return None
+        for entry in fields["traffic_bytes_per_launch"]:
+            if entry[0] == op:
+                return int(entry[1])
+    except (KeyError, IndexError, OSError, ValueError):
+        return None
+    return None
 
 
 def parse_args(argv=None):
@@ -45,7 +81,95 @@ def parse_args(argv=None):
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="target duration of the CPU-baseline sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-secondary", action="store_true",
+                   help="skip the batched-dot, GEMM and matvec measurements")
     return p.parse_args(argv)
+
+
+def _time_launches(fn, reps: int, stream) -> float:
+    """Mean milliseconds per call of fn() over reps calls, HIP events on the
+    launch stream (one untimed call first)."""
+    import torch
+
+    fn()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(reps):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / reps
+
+
+def secondary(stream) -> dict:
+    """The other float-float workloads, one line each (not part of the step)."""
+    import torch
+
+    import ff_inputs as fi
+    import paper_cs_0603115_amd as ff
+    from paper_cs_0603115_amd import autotune
+
+    dev = torch.device("cuda:0")
+    out = {}
+
+    log("[bench] batched dot: 4096 vectors, lengths floor(2^U[6,20])")
+    x, y, offs = fi.batched_dot(115003, device=dev)
+    total = x.numel()
+    cfg = autotune.dot_cfg(x, y, offs)
+    res = ff.ff_empty((offs.numel() - 1,), device=dev)
+    ws = torch.empty(ff.ff_dot_batched_workspace_size(total, offs.numel() - 1, cfg),
+                     dtype=torch.uint8, device=dev)
+    ms = _time_launches(lambda: ff.ff_dot_batched(x, y, offs, cfg=cfg, out=res, workspace=ws,
+                                                  stream=stream), 10, stream)
+    gbs = 8 * total / (ms * 1e-3) / 1e9
+    out["dot_batched"] = {"elements": total, "ms": round(ms, 4), "elements/s": total / (ms * 1e-3),
+                          "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                          "cfg": list(cfg)}
+    del x, y, offs, res, ws
+    torch.cuda.empty_cache()
+
+    n = 4096
+    log(f"[bench] ff GEMM {n}^3: sliced int8, sliced BF16, FMA loop")
+    A = fi.gaussian_ff((n, n), 115004, device=dev)
+    B = fi.gaussian_ff((n, n), 115014, device=dev)
+    C = ff.ff_empty((n, n), device=dev)
+    flops = 2.0 * n * n * n
+    gemm = {}
+    for name, algo, reps in (("sliced_i8", ff.GEMM_SLICED_I8, 5),
+                             ("sliced_bf16", ff.GEMM_SLICED_BF16, 5),
+                             ("fma_loop", ff.GEMM_FMA_LOOP, 2)):
+        wsg = torch.empty(max(ff.ff_gemm_workspace_size(n, n, n, algo), 1), dtype=torch.uint8,
+                          device=dev)
+        ms = _time_launches(lambda: ff.ff_gemm(A, B, algo=algo, out=C, workspace=wsg,
+                                               stream=stream), reps, stream)
+        gemm[name] = {"ms": round(ms, 3), "ff_TFLOP/s": round(flops / (ms * 1e-3) / 1e12, 2)}
+        del wsg
+    gemm["speedup_i8_vs_fma_loop"] = round(gemm["fma_loop"]["ms"] / gemm["sliced_i8"]["ms"], 1)
+    gemm["speedup_bf16_vs_fma_loop"] = round(gemm["fma_loop"]["ms"] / gemm["sliced_bf16"]["ms"], 1)
+    out["gemm_4096"] = gemm
+    del A, B, C
+    torch.cuda.empty_cache()
+
+    m = 8192
+    log(f"[bench] ff matvec {m}^2 forward and backward (fast vs plain)")
+    A = fi.gaussian_ff((m, m), 115005, device=dev)
+    xv = fi.gaussian_ff((m,), 115006, device=dev)
+    g = torch.stack([fi.gaussian_f32((m,), 115007, device=dev), torch.zeros(m, device=dev)])
+    mv = {}
+    for name, algo in (("fast", ff.MATVEC_FAST), ("plain", ff.MATVEC_PLAIN)):
+        fwd = _time_launches(lambda: ff.ff_matvec(A, xv, algo=algo, stream=stream), 10, stream)
+        bwd = _time_launches(lambda: ff.ff_matvec_backward(A, xv, g, algo=algo, stream=stream),
+                             5, stream)
+        mv[name] = {"forward_ms": round(fwd, 4), "backward_ms": round(bwd, 4),
+                    "forward_GB/s": round(8 * m * m / (fwd * 1e-3) / 1e9, 1),
+                    "backward_GB/s": round(16 * m * m / (bwd * 1e-3) / 1e9, 1)}
+    mv["backward_speedup_fast_vs_plain"] = round(mv["plain"]["backward_ms"] / mv["fast"]["backward_ms"], 1)
+    mv["forward_speedup_fast_vs_plain"] = round(mv["plain"]["forward_ms"] / mv["fast"]["forward_ms"], 1)
+    out["matvec_8192"] = mv
+    del A, xv, g
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(a, b, target_s: float):
@@ -173,7 +297,8 @@ def main(argv=None) -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": profiled_traffic(dominant, n),
+            "traffic_source": os.path.relpath(PROFILE_SUMMARY, _ROOT),
         },
         "per_op": per_op,
         "copy_probe": {"ms": round(copy_ms, 5), "GB/s": round(copy_gbs, 1),
@@ -182,6 +307,10 @@ def main(argv=None) -> int:
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle) on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(a, b, args.cpu_seconds)
+    if not args.no_secondary:
+        del a, b, r
+        torch.cuda.empty_cache()
+        result["secondary"] = secondary(stream)
     print(json.dumps(result), flush=True)
     return 0
 
