@@ -30,12 +30,13 @@
 // most one unit of 2^(e_i - P) per entry), the dropped pairs (< 2^-47 of
 // 2^(e_i + f_j) K), and the final rounding (2^-48 |C_ij|).
 //
-// Data layout of the digit planes (workspace): for each slice t and 64 x 64-
-// byte tile (64 rows of A, or 64 columns of B, by one K-stage of 64 bytes:
-// 64 int8 or 32 BF16 digits), the 4 KiB tile is contiguous; within a row the
-// four 16-byte chunks are permuted by chunk ^ ((row >> 1) & 3), so that the
-// matrix-core operand reads from LDS (8 rows x 16 bytes per LDS cycle) hit
-// distinct banks.  B is stored transposed (K contiguous per column).
+// Data layout of the digit planes (workspace): for each slice t and tile of
+// 64 rows of A (or 64 columns of B) by one K-stage of 32 bytes (32 int8 or 16
+// BF16 digits: one matrix-core K-step), the 2 KiB tile is contiguous, so a
+// stage is copied into LDS with straight 1 KiB wavefront loads; within a row
+// the two 16-byte chunks are swapped on a row pattern (tile_swizzle) so that
+// the operand reads hit distinct LDS banks.  B is stored transposed (K
+// contiguous per column).
 #include "ff_device.h"
 #include "ff_host.h"
 
@@ -122,7 +123,9 @@ __global__ __launch_bounds__(256) void gemm_fma_loop(int64_t M, int64_t N, int64
 constexpr int kS = 7;                 // digits per operand
 constexpr int kP = 8 * kS - 2;        // fixed-point bits: |X| <= 2^kP
 constexpr int kTile = 64;             // rows (A) / columns (B) per tile
-constexpr int kTileBytes = 64 * 64;   // one slice tile: 64 rows x 64 bytes
+constexpr int kRowBytes = 32;         // digit bytes of one tile row per K-stage
+constexpr int kTileBytes = kTile * kRowBytes;       // 2 KiB
+constexpr int kStageBytes = 2 * kS * kTileBytes;    // A and B tiles of all slices: 28 KiB
 constexpr int kEpiShift = 8 * (kS - 1) - 2 * kP;   // C = T 2^(e + f + kEpiShift)
 constexpr int64_t kMaxKChunk = 16384; // int32 accumulators stay exact below this
 
@@ -130,16 +133,18 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) void *lds_void_ptr;
+typedef const __attribute__((address_space(1))) void *global_void_ptr;
 
 struct DigitsI8 {
     static constexpr int kEsize = 1;
-    static constexpr int kStageK = 64;        // digits per tile row per stage
-    static constexpr int kExtractStages = 0;  // int32 accumulation: never
+    static constexpr int kStageK = kRowBytes;      // 32 digits: one i8 MFMA K-step
+    static constexpr int kExtractStages = 0;       // int32 accumulation: never
 };
 struct DigitsBF16 {
     static constexpr int kEsize = 2;
-    static constexpr int kStageK = 32;
-    static constexpr int kExtractStages = 4;  // 128 k per FP32 window
+    static constexpr int kStageK = kRowBytes / 2;  // 16 digits: one BF16 MFMA K-step
+    static constexpr int kExtractStages = 8;       // drain FP32 every 128 k
 };
 
 __device__ __forceinline__ uint32_t f32_bits(float v) { return __float_as_uint(v); }
@@ -193,24 +198,32 @@ __device__ __forceinline__ void entry_digits(float hi, float lo, int e, int d[kS
     }
 }
 
+// Bit pattern of digit d in the plane's element type.
 template <class Dg>
-__device__ __forceinline__ void put_digit(uint8_t *chunk, int q, int d)
+__device__ __forceinline__ uint32_t digit_bits(int d)
 {
-    if constexpr (Dg::kEsize == 1) {
-        chunk[q] = static_cast<uint8_t>(static_cast<int8_t>(d));
-    } else {
+    if constexpr (Dg::kEsize == 1)
+        return static_cast<uint32_t>(d) & 0xffu;
+    else
         // |d| <= 128 has at most 8 significant bits: the BF16 pattern is the
         // upper half of the binary32 pattern, exactly.
-        const uint16_t bf = static_cast<uint16_t>(f32_bits(static_cast<float>(d)) >> 16);
-        reinterpret_cast<uint16_t *>(chunk)[q] = bf;
-    }
+        return f32_bits(static_cast<float>(d)) >> 16;
 }
 
-__device__ __forceinline__ int64_t tile_offset(int t, int bi, int bk, int nB, int nBK, int row,
-                                               int chunk)
+// Byte offset of (row, 16-byte chunk) inside a 2 KiB tile.  Rows are 32
+// bytes; the two chunks of a row are swapped when bit 2 xor bit 3 of the row
+// is set.  The operand reads take 16 consecutive rows at one logical chunk
+// per 256-byte LDS cycle (64 banks of 4 bytes on gfx950): rows r and r + 8
+// share a bank group unless their chunks differ, which this swizzle
+// guarantees -- and 8-row groups stay conflict-free as well.
+__device__ __forceinline__ int tile_swizzle(int row, int chunk)
 {
-    return ((static_cast<int64_t>(t) * nB + bi) * nBK + bk) * kTileBytes + row * 64 +
-           ((chunk ^ ((row >> 1) & 3)) * 16);
+    return row * kRowBytes + ((chunk ^ (((row >> 2) ^ (row >> 3)) & 1)) * 16);
+}
+
+__device__ __forceinline__ int64_t tile_base(int t, int bi, int bk, int nB, int nBK)
+{
+    return ((static_cast<int64_t>(t) * nB + bi) * nBK + bk) * kTileBytes;
 }
 
 __global__ __launch_bounds__(256) void fill_u32(uint32_t *p, int64_t n)
@@ -259,76 +272,89 @@ __global__ __launch_bounds__(256) void absmax_cols(int64_t K, int64_t N,
         atomicMax(&colmax[j], m);
 }
 
-// A digit planes: one workgroup per (64-row tile, K stage); thread = one
-// 16-byte chunk of one row, all S slices.
+// One 16-byte chunk of every slice for the entries (r, k0 .. k0 + per - 1)
+// of a row (A) or column (B): packs the digits into four 32-bit words per
+// slice and stores them at the swizzled tile position.
+template <class Dg, class Load>
+__device__ __forceinline__ void slice_chunk(Load load, bool row_ok, int64_t k0, int64_t K, int e,
+                                            uint8_t *__restrict__ planes, int64_t plane_tile0,
+                                            int64_t slice_stride, int in_tile)
+{
+    constexpr int kPer = 16 / Dg::kEsize;         // digits per chunk
+    constexpr int kPerWord = 4 / Dg::kEsize;      // digits per 32-bit word
+    uint32_t w[kS][4];
+#pragma unroll
+    for (int t = 0; t < kS; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            w[t][q] = 0u;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int64_t k = k0 + q;
+        int d[kS];
+        if (row_ok && k < K) {
+            float hi, lo;
+            load(k, hi, lo);
+            entry_digits(hi, lo, e, d);
+        } else {
+#pragma unroll
+            for (int t = 0; t < kS; ++t)
+                d[t] = 0;
+        }
+#pragma unroll
+        for (int t = 0; t < kS; ++t)
+            w[t][q / kPerWord] |= digit_bits<Dg>(d[t]) << (8 * Dg::kEsize * (q % kPerWord));
+    }
+#pragma unroll
+    for (int t = 0; t < kS; ++t)
+        *reinterpret_cast<uint4 *>(planes + plane_tile0 + t * slice_stride + in_tile) =
+            make_uint4(w[t][0], w[t][1], w[t][2], w[t][3]);
+}
+
+// A digit planes: workgroup = (64-row tile, K stage), 128 threads, thread =
+// (row, chunk).
 template <class Dg>
-__global__ __launch_bounds__(256) void slice_rows(int64_t M, int64_t K,
+__global__ __launch_bounds__(128) void slice_rows(int64_t M, int64_t K,
                                                   const float *__restrict__ Ah,
                                                   const float *__restrict__ Al, int64_t lda,
                                                   const uint32_t *__restrict__ rowmax, int nBI,
                                                   int nBK, uint8_t *__restrict__ planes)
 {
-    constexpr int kPerChunk = 16 / Dg::kEsize;
     const int bk = blockIdx.x, bi = blockIdx.y;
-    const int row = threadIdx.x >> 2, chunk = threadIdx.x & 3;
+    const int row = threadIdx.x >> 1, chunk = threadIdx.x & 1;
     const int64_t i = static_cast<int64_t>(bi) * kTile + row;
-    const int64_t kb = static_cast<int64_t>(bk) * Dg::kStageK + chunk * kPerChunk;
-    alignas(16) uint8_t out[kS][16];
-    const int e = i < M ? exponent_bound(rowmax[i]) : 0;
-#pragma unroll
-    for (int q = 0; q < kPerChunk; ++q) {
-        const int64_t k = kb + q;
-        int d[kS];
-        if (i < M && k < K)
-            entry_digits(Ah[i * lda + k], Al[i * lda + k], e, d);
-        else
-#pragma unroll
-            for (int t = 0; t < kS; ++t)
-                d[t] = 0;
-#pragma unroll
-        for (int t = 0; t < kS; ++t)
-            put_digit<Dg>(out[t], q, d[t]);
-    }
-#pragma unroll
-    for (int t = 0; t < kS; ++t)
-        *reinterpret_cast<uint4 *>(planes + tile_offset(t, bi, bk, nBI, nBK, row, chunk)) =
-            *reinterpret_cast<const uint4 *>(out[t]);
+    const bool ok = i < M;
+    const int e = ok ? exponent_bound(rowmax[i]) : 0;
+    const int64_t k0 = static_cast<int64_t>(bk) * Dg::kStageK + chunk * (16 / Dg::kEsize);
+    auto load = [&](int64_t k, float &hi, float &lo) {
+        hi = Ah[i * lda + k];
+        lo = Al[i * lda + k];
+    };
+    slice_chunk<Dg>(load, ok, k0, K, e, planes, tile_base(0, bi, bk, nBI, nBK),
+                    static_cast<int64_t>(nBI) * nBK * kTileBytes, tile_swizzle(row, chunk));
 }
 
-// B^T digit planes: one workgroup per (64-column tile, K stage); lanes take
-// consecutive columns (coalesced reads of B's rows).
+// B^T digit planes: workgroup = (64-column tile, K stage), 128 threads;
+// lanes take consecutive columns (coalesced reads of B's rows).
 template <class Dg>
-__global__ __launch_bounds__(256) void slice_cols(int64_t K, int64_t N,
+__global__ __launch_bounds__(128) void slice_cols(int64_t K, int64_t N,
                                                   const float *__restrict__ Bh,
                                                   const float *__restrict__ Bl, int64_t ldb,
                                                   const uint32_t *__restrict__ colmax, int nBJ,
                                                   int nBK, uint8_t *__restrict__ planes)
 {
-    constexpr int kPerChunk = 16 / Dg::kEsize;
     const int bk = blockIdx.x, bj = blockIdx.y;
     const int col = threadIdx.x & 63, chunk = threadIdx.x >> 6;
     const int64_t j = static_cast<int64_t>(bj) * kTile + col;
-    const int64_t kb = static_cast<int64_t>(bk) * Dg::kStageK + chunk * kPerChunk;
-    alignas(16) uint8_t out[kS][16];
-    const int e = j < N ? exponent_bound(colmax[j]) : 0;
-#pragma unroll
-    for (int q = 0; q < kPerChunk; ++q) {
-        const int64_t k = kb + q;
-        int d[kS];
-        if (j < N && k < K)
-            entry_digits(Bh[k * ldb + j], Bl[k * ldb + j], e, d);
-        else
-#pragma unroll
-            for (int t = 0; t < kS; ++t)
-                d[t] = 0;
-#pragma unroll
-        for (int t = 0; t < kS; ++t)
-            put_digit<Dg>(out[t], q, d[t]);
-    }
-#pragma unroll
-    for (int t = 0; t < kS; ++t)
-        *reinterpret_cast<uint4 *>(planes + tile_offset(t, bj, bk, nBJ, nBK, col, chunk)) =
-            *reinterpret_cast<const uint4 *>(out[t]);
+    const bool ok = j < N;
+    const int e = ok ? exponent_bound(colmax[j]) : 0;
+    const int64_t k0 = static_cast<int64_t>(bk) * Dg::kStageK + chunk * (16 / Dg::kEsize);
+    auto load = [&](int64_t k, float &hi, float &lo) {
+        hi = Bh[k * ldb + j];
+        lo = Bl[k * ldb + j];
+    };
+    slice_chunk<Dg>(load, ok, k0, K, e, planes, tile_base(0, bj, bk, nBJ, nBK),
+                    static_cast<int64_t>(nBJ) * nBK * kTileBytes, tile_swizzle(col, chunk));
 }
 
 // Round the integer t to 24 bits, nearest-even: t ~ mant 2^E (E >= 0).
@@ -394,31 +420,61 @@ template <class Dg> struct AccOf;
 template <> struct AccOf<DigitsI8> { using T = i32x16; };
 template <> struct AccOf<DigitsBF16> { using T = f32x16; };
 
-// The sliced product.  Workgroup = 4 wavefronts = 64 x 64 outputs; wavefront
-// (wm, wn) owns a 32 x 32 block held as S diagonal accumulators of one
-// 32x32 matrix-core tile each.  K-stages [bk0, bk1) are streamed through
-// double-buffered LDS (all S slices of the A and B tiles per stage).
-template <class Dg>
-__global__ __launch_bounds__(256) void gemm_sliced(int64_t M, int64_t N, int nBI, int nBJ,
-                                                   int nBK, int bk0, int bk1,
-                                                   const uint8_t *__restrict__ Ap,
-                                                   const uint8_t *__restrict__ Bp,
-                                                   const uint32_t *__restrict__ rowmax,
-                                                   const uint32_t *__restrict__ colmax,
-                                                   float *__restrict__ Ch,
-                                                   float *__restrict__ Cl, int64_t ldc,
-                                                   int accumulate)
+// One LDS slot of the stage ring.  Each slot is a distinct LDS variable, so
+// the compiler can tell a slot being read from one being filled by DMA.
+template <int BYTES, int I>
+__device__ __forceinline__ uint8_t *lds_slot()
+{
+    __shared__ uint4 slot[BYTES / 16];
+    return reinterpret_cast<uint8_t *>(slot);
+}
+
+// Launch shape of the sliced product: WM x WN wavefronts (256 or 512
+// threads), each owning a 32 x 32 block of C as S diagonal accumulators, and
+// a ring of NST K-stages in LDS.
+template <class Dg> struct SlicedShape;
+// int8: 8 wavefronts (2 per SIMD, <= 256 registers each), 128 x 64 outputs,
+// 2 x 42 KiB stages.
+template <> struct SlicedShape<DigitsI8> {
+    static constexpr int WM = 4, WN = 2, NST = 2, WAVES_PER_SIMD = 2;
+};
+// BF16: FP32 and int32 diagonal accumulators need ~400 registers, so one
+// wavefront per SIMD: 4 wavefronts, 64 x 64 outputs, 2 x 28 KiB stages.
+template <> struct SlicedShape<DigitsBF16> {
+    static constexpr int WM = 2, WN = 2, NST = 2, WAVES_PER_SIMD = 1;
+};
+
+// The sliced product for one output block of (32 WM) x (32 WN).  Each K-stage
+// is the block's digit tiles (A and B, all S slices, 2 KiB per 64-row tile)
+// copied from memory straight into LDS with 16-byte global_load_lds (no
+// staging registers); stage k + 1 is in flight while the digit-pair MFMAs of
+// stage k run.
+template <class Dg, int WM, int WN, int NST, int WPS>
+__global__ __launch_bounds__(64 * WM * WN, WPS) void gemm_sliced(
+    int64_t M, int64_t N, int nBI, int nBJ, int nBK, int bk0, int bk1,
+    const uint8_t *__restrict__ Ap, const uint8_t *__restrict__ Bp,
+    const uint32_t *__restrict__ rowmax, const uint32_t *__restrict__ colmax,
+    float *__restrict__ Ch, float *__restrict__ Cl, int64_t ldc, int accumulate)
 {
     using Acc = typename AccOf<Dg>::T;
-    __shared__ uint4 lds_raw[2 * 2 * kS * kTileBytes / 16];   // 112 KiB
-    uint8_t *lds = reinterpret_cast<uint8_t *>(lds_raw);
-    // lds[buf][op][slice][4096]
-    auto tile_at = [&](int buf, int op, int t) {
-        return lds + ((buf * 2 + op) * kS + t) * kTileBytes;
-    };
+    constexpr int kWaves = WM * WN;
+    constexpr int kTA = WM / 2, kTB = WN / 2;             // 64-row tiles per slice
+    constexpr int kSlotBytes = kS * (kTA + kTB) * kTileBytes;
+    constexpr int kHalves = 2 * kS * (kTA + kTB);         // 1 KiB wavefront loads per stage
+    constexpr int kQ = kHalves / kWaves, kR = kHalves % kWaves;
+    uint8_t *slots[NST];
+    slots[0] = lds_slot<kSlotBytes, 0>();
+    slots[1] = lds_slot<kSlotBytes, 1>();
+    if constexpr (NST > 2)
+        slots[2] = lds_slot<kSlotBytes, 2>();
+    if constexpr (NST > 3)
+        slots[3] = lds_slot<kSlotBytes, 3>();
+
     const int bj = blockIdx.x, bi = blockIdx.y;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WN, wn = wave % WN;
+    const int64_t a_slice = static_cast<int64_t>(nBI) * nBK * kTileBytes;
+    const int64_t b_slice = static_cast<int64_t>(nBJ) * nBK * kTileBytes;
 
     Acc acc[kS];
     i32x16 iacc[kS];
@@ -431,52 +487,63 @@ __global__ __launch_bounds__(256) void gemm_sliced(int64_t M, int64_t N, int nBI
         }
     }
 
-    uint4 stage_a[kS], stage_b[kS];
-    auto fetch = [&](int bk) {
+    // Half-tile h of a stage: A halves first (slice-major, tile, half),
+    // then B halves.  Wavefront w loads halves w, w + kWaves, ...
+    auto fetch = [&](int bk, uint8_t *slot) {
 #pragma unroll
-        for (int t = 0; t < kS; ++t) {
-            stage_a[t] = reinterpret_cast<const uint4 *>(
-                Ap + ((static_cast<int64_t>(t) * nBI + bi) * nBK + bk) * kTileBytes)[tid];
-            stage_b[t] = reinterpret_cast<const uint4 *>(
-                Bp + ((static_cast<int64_t>(t) * nBJ + bj) * nBK + bk) * kTileBytes)[tid];
-        }
-    };
-    auto stash = [&](int buf) {
-#pragma unroll
-        for (int t = 0; t < kS; ++t) {
-            reinterpret_cast<uint4 *>(tile_at(buf, 0, t))[tid] = stage_a[t];
-            reinterpret_cast<uint4 *>(tile_at(buf, 1, t))[tid] = stage_b[t];
+        for (int j = 0; j < kQ + (kR ? 1 : 0); ++j) {
+            const int h = wave + j * kWaves;
+            if (h < kHalves) {
+                const int tile = h >> 1, half = h & 1;
+                const uint8_t *src;
+                if (tile < kS * kTA) {
+                    const int t = tile / kTA, tt = tile % kTA;
+                    src = Ap + t * a_slice + tile_base(0, bi * kTA + tt, bk, nBI, nBK);
+                } else {
+                    const int tb = tile - kS * kTA;
+                    const int t = tb / kTB, tt = tb % kTB;
+                    src = Bp + t * b_slice + tile_base(0, bj * kTB + tt, bk, nBJ, nBK);
+                }
+                src += half * 1024 + lane * 16;
+                uint8_t *dst = slot + tile * kTileBytes + half * 1024;
+                // address-space conversions (generic -> global / LDS) need C casts
+                __builtin_amdgcn_global_load_lds((global_void_ptr)(const void *)src,
+                                                 (lds_void_ptr)(void *)dst, 16, 0, 0);
+            }
         }
     };
 
-    const int ra = wm * 32 + (lane & 31);   // A tile row of this lane
-    const int rb = wn * 32 + (lane & 31);   // B tile row (= C column) of this lane
-    if (bk0 < bk1) {
-        fetch(bk0);
-        stash(0);
-    }
-    __syncthreads();
-    for (int bk = bk0; bk < bk1; ++bk) {
-        const int buf = (bk - bk0) & 1;
-        if (bk + 1 < bk1)
-            fetch(bk + 1);
+    // Operand rows of this lane: A row wm*32 + lane%32 lives in A tile
+    // (wm / 2) at row 32*(wm % 2) + lane%32; likewise B.
+    const int ta = wm >> 1, rla = 32 * (wm & 1) + (lane & 31);
+    const int tb = wn >> 1, rlb = 32 * (wn & 1) + (lane & 31);
+    const int oa = ta * kTileBytes + tile_swizzle(rla, lane >> 5);
+    const int ob = kS * kTA * kTileBytes + tb * kTileBytes + tile_swizzle(rlb, lane >> 5);
+
+    // One K-stage: the fragments of stage bk are read from LDS into
+    // registers first, then the DMA of stage bk + 1 is issued into the other
+    // slot (free: every wavefront finished reading it before the last
+    // barrier), then the digit-pair MFMAs run from registers while the DMA
+    // flies; the stage ends by waiting for this wavefront's DMA share and a
+    // barrier.  (The compiler orders LDS reads after an LDS DMA with a full
+    // vmcnt wait; reading before issuing keeps that wait off the critical
+    // path.)
+    auto stage = [&](const uint8_t *slot, uint8_t *next_slot, int bk) {
+        uint4 fa[kS], fb[kS];
 #pragma unroll
-        for (int step = 0; step < 2; ++step) {
-            const int chunk = 2 * step + (lane >> 5);
-            const int oa = ra * 64 + ((chunk ^ ((ra >> 1) & 3)) * 16);
-            const int ob = rb * 64 + ((chunk ^ ((rb >> 1) & 3)) * 16);
-            uint4 fa[kS], fb[kS];
-#pragma unroll
-            for (int t = 0; t < kS; ++t) {
-                fa[t] = *reinterpret_cast<const uint4 *>(tile_at(buf, 0, t) + oa);
-                fb[t] = *reinterpret_cast<const uint4 *>(tile_at(buf, 1, t) + ob);
-            }
-#pragma unroll
-            for (int d = 0; d < kS; ++d)
-#pragma unroll
-                for (int t = 0; t <= d; ++t)
-                    acc[d] = mma(fa[t], fb[d - t], acc[d], Dg{});
+        for (int t = 0; t < kS; ++t) {
+            fa[t] = *reinterpret_cast<const uint4 *>(slot + t * kTA * kTileBytes + oa);
+            fb[t] = *reinterpret_cast<const uint4 *>(slot + t * kTB * kTileBytes + ob);
         }
+        if (bk + 1 < bk1)
+            fetch(bk + 1, next_slot);
+        // digit pairs (t, u), t + u <= S - 1; consecutive instructions feed
+        // different diagonal accumulators
+#pragma unroll
+        for (int u = 0; u < kS; ++u)
+#pragma unroll
+            for (int t = 0; t + u < kS; ++t)
+                acc[t + u] = mma(fa[t], fb[u], acc[t + u], Dg{});
         if constexpr (Dg::kExtractStages > 0) {
             if ((bk - bk0 + 1) % Dg::kExtractStages == 0 || bk + 1 == bk1) {
 #pragma unroll
@@ -488,19 +555,30 @@ __global__ __launch_bounds__(256) void gemm_sliced(int64_t M, int64_t N, int nBI
                     }
             }
         }
+        // keep the MFMAs above the barrier: its vmcnt wait must not be
+        // scheduled before the work it is meant to overlap
+        __builtin_amdgcn_sched_barrier(0);
+        __syncthreads();   // waits for this wavefront's DMA, then the barrier
+    };
+
+    static_assert(NST == 2, "two-slot ring");
+    if (bk0 < bk1)
+        fetch(bk0, slots[0]);
+    __syncthreads();
+    for (int bk = bk0; bk < bk1; bk += 2) {
+        stage(slots[0], slots[1], bk);
         if (bk + 1 < bk1)
-            stash(buf ^ 1);
-        __syncthreads();
+            stage(slots[1], slots[0], bk + 1);
     }
 
     // Epilogue: lane holds C[8*(r/4) + 4*(lane/32) + (r%4)][lane%32] of the
     // wavefront's 32x32 block for r = 0..15.
-    const int64_t j = static_cast<int64_t>(bj) * kTile + wn * 32 + (lane & 31);
+    const int64_t j = static_cast<int64_t>(bj) * (32 * WN) + wn * 32 + (lane & 31);
     const int fj = j < N ? exponent_bound(colmax[j]) : 0;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int64_t i = static_cast<int64_t>(bi) * kTile + wm * 32 + m;
+        const int64_t i = static_cast<int64_t>(bi) * (32 * WM) + wm * 32 + m;
         if (i >= M || j >= N)
             continue;
         __int128 T = 0;
@@ -530,11 +608,13 @@ struct SliceGeom {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-inline SliceGeom slice_geom(int64_t M, int64_t N, int64_t K, int esize, int stage_k)
+inline SliceGeom slice_geom(int64_t M, int64_t N, int64_t K, int stage_k)
 {
     SliceGeom g;
-    g.nBI = static_cast<int>((M + kTile - 1) / kTile);
-    g.nBJ = static_cast<int>((N + kTile - 1) / kTile);
+    // tile counts padded to even numbers: a workgroup covers up to two
+    // 64-row (or 64-column) tiles; the padding tiles hold zero digits
+    g.nBI = 2 * static_cast<int>((M + 2 * kTile - 1) / (2 * kTile));
+    g.nBJ = 2 * static_cast<int>((N + 2 * kTile - 1) / (2 * kTile));
     g.nBK = static_cast<int>((K + stage_k - 1) / stage_k);
     g.plane_a = static_cast<size_t>(kS) * g.nBI * g.nBK * kTileBytes;
     g.plane_b = static_cast<size_t>(kS) * g.nBJ * g.nBK * kTileBytes;
@@ -543,7 +623,6 @@ inline SliceGeom slice_geom(int64_t M, int64_t N, int64_t K, int esize, int stag
     g.off_a = g.off_colmax + align256(sizeof(uint32_t) * N);
     g.off_b = g.off_a + align256(g.plane_a);
     g.total = g.off_b + align256(g.plane_b);
-    (void)esize;
     return g;
 }
 
@@ -552,7 +631,7 @@ ff_status sliced_gemm(int64_t M, int64_t N, int64_t K, const float *Ah, const fl
                       int64_t lda, const float *Bh, const float *Bl, int64_t ldb, float *Ch,
                       float *Cl, int64_t ldc, void *ws, size_t ws_bytes, hipStream_t st)
 {
-    const SliceGeom g = slice_geom(M, N, K, Dg::kEsize, Dg::kStageK);
+    const SliceGeom g = slice_geom(M, N, K, Dg::kStageK);
     if (!ws)
         return FF_ERR_NULL;
     if (ws_bytes < g.total)
@@ -567,8 +646,9 @@ ff_status sliced_gemm(int64_t M, int64_t N, int64_t K, const float *Ah, const fl
     uint8_t *Ap = reinterpret_cast<uint8_t *>(base + g.off_a);
     uint8_t *Bp = reinterpret_cast<uint8_t *>(base + g.off_b);
 
-    const int64_t nfill = static_cast<int64_t>((g.off_a) / sizeof(uint32_t));
-    hipLaunchKernelGGL(fill_u32, dim3(static_cast<unsigned>(ffh::cdiv(nfill, 256) < 4096 ? ffh::cdiv(nfill, 256) : 4096)),
+    const int64_t nfill = static_cast<int64_t>(g.off_a / sizeof(uint32_t));
+    const int64_t fill_blocks = ffh::cdiv(nfill, 256);
+    hipLaunchKernelGGL(fill_u32, dim3(static_cast<unsigned>(fill_blocks < 4096 ? fill_blocks : 4096)),
                        dim3(256), 0, st, rowmax, nfill);
     if (K > 0) {
         hipLaunchKernelGGL(absmax_rows,
@@ -579,18 +659,21 @@ ff_status sliced_gemm(int64_t M, int64_t N, int64_t K, const float *Ah, const fl
                            dim3(static_cast<unsigned>(ffh::cdiv(N, 256)),
                                 static_cast<unsigned>(ffh::cdiv(K, 256))),
                            dim3(256), 0, st, K, N, Bh, ldb, colmax);
-        hipLaunchKernelGGL((slice_rows<Dg>), dim3(g.nBK, g.nBI), dim3(256), 0, st, M, K, Ah, Al,
+        hipLaunchKernelGGL((slice_rows<Dg>), dim3(g.nBK, g.nBI), dim3(128), 0, st, M, K, Ah, Al,
                            lda, rowmax, g.nBI, g.nBK, Ap);
-        hipLaunchKernelGGL((slice_cols<Dg>), dim3(g.nBK, g.nBJ), dim3(256), 0, st, K, N, Bh, Bl,
+        hipLaunchKernelGGL((slice_cols<Dg>), dim3(g.nBK, g.nBJ), dim3(128), 0, st, K, N, Bh, Bl,
                            ldb, colmax, g.nBJ, g.nBK, Bp);
     }
+    using Sh = SlicedShape<Dg>;
     const int stages_per_chunk = static_cast<int>(kMaxKChunk / Dg::kStageK);
+    const dim3 grid(static_cast<unsigned>(g.nBJ / (Sh::WN / 2)),
+                    static_cast<unsigned>(g.nBI / (Sh::WM / 2)));
     int bk0 = 0;
     do {
         const int bk1 = (bk0 + stages_per_chunk < g.nBK) ? bk0 + stages_per_chunk : g.nBK;
-        hipLaunchKernelGGL((gemm_sliced<Dg>), dim3(g.nBJ, g.nBI), dim3(256), 0, st, M, N,
-                           g.nBI, g.nBJ, g.nBK, bk0, bk1, Ap, Bp, rowmax, colmax, Ch, Cl, ldc,
-                           bk0 > 0 ? 1 : 0);
+        hipLaunchKernelGGL((gemm_sliced<Dg, Sh::WM, Sh::WN, Sh::NST, Sh::WAVES_PER_SIMD>), grid,
+                           dim3(64 * Sh::WM * Sh::WN), 0, st, M, N, g.nBI, g.nBJ, g.nBK, bk0, bk1,
+                           Ap, Bp, rowmax, colmax, Ch, Cl, ldc, bk0 > 0 ? 1 : 0);
         bk0 = bk1;
     } while (bk0 < g.nBK);
     return ffh::launch_status();
@@ -608,8 +691,8 @@ size_t ff_gemm_workspace_size(int64_t M, int64_t N, int64_t K, int32_t algo)
         return 0;
     switch (algo) {
     case FF_GEMM_FMA_LOOP: return 0;
-    case FF_GEMM_SLICED_BF16: return slice_geom(M, N, K, 2, DigitsBF16::kStageK).total;
-    case FF_GEMM_SLICED_I8: return slice_geom(M, N, K, 1, DigitsI8::kStageK).total;
+    case FF_GEMM_SLICED_BF16: return slice_geom(M, N, K, DigitsBF16::kStageK).total;
+    case FF_GEMM_SLICED_I8: return slice_geom(M, N, K, DigitsI8::kStageK).total;
     default: return 0;
     }
 }
