@@ -210,8 +210,9 @@ def test_gemm_validation_and_workspace():
     assert size(64, 64, 64, 0) == 0                       # FMA loop needs none
     w8, w16 = size(100, 70, 333, 2), size(100, 70, 333, 1)
     assert w8 > 0 and w16 > w8
-    # digit planes: 7 slices x 64-row tiles x 64-byte stages
-    assert w8 >= 7 * (128 + 128) * 384
+    # int8 digit planes: 7 slices x (rows and columns padded to 128) x K
+    # padded to the 32-byte stage
+    assert w8 >= 7 * (128 + 128) * 352
     assert size(-1, 4, 4, 2) == 0 and size(4, 4, 4, 9) == 0
     P = [4096 * (k + 1) for k in range(6)]
     ws = 1 << 24
