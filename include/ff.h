@@ -130,13 +130,14 @@ ff_status ff_div(const float *a_hi, const float *a_lo, const float *b_hi,
  * paper defines no reduction; compensated summation is its stated future
  * work (section 7).
  *
- * Execution: one small planning launch (chunk table, counters) and ONE
- * persistent launch that walks all chunks of all vectors.  Each chunk of
- * `cfg->chunk` elements is reduced by one workgroup (per-lane float-float
- * accumulators, a wavefront butterfly of Add22 over lane shuffles, then the
- * wavefronts' partials in order through LDS) into a float-float partial;
- * the workgroup that completes a vector's last chunk combines that vector's
- * partials with an Add22 tree of fixed shape.  No floating-point atomics are
+ * Execution: four launches on `stream`: a planning launch (chunk counts and
+ * their scan), one writing each chunk's element range, ONE persistent
+ * launch that walks all chunks of all vectors, and one combining each
+ * vector's partials.  Each chunk of `cfg->chunk` elements is reduced by one
+ * workgroup (per-lane float-float accumulators, a wavefront butterfly of
+ * Add22 over lane shuffles, then the wavefronts' partials in order through
+ * LDS) into a float-float partial; one wavefront per vector then adds the
+ * vector's partials with an Add22 tree of fixed shape.  No atomics are
  * used: for a given cfg the result is bitwise reproducible run to run.
  * Different cfg values may give different (equally valid) last bits.
  *
@@ -146,10 +147,10 @@ ff_status ff_div(const float *a_hi, const float *a_lo, const float *b_hi,
 
 /* Launch shape of the batched dot.  All-zero fields select the defaults. */
 typedef struct ff_dot_cfg {
-    int32_t block;  /* threads per workgroup: 256 or 512 (0: 256)           */
+    int32_t block;  /* threads per workgroup: 256 or 512 (0: 512)           */
     int32_t chunk;  /* elements per chunk, a multiple of 4, >= 64 (0: 16384) */
-    int32_t grid;   /* persistent workgroups; 0: 8 per compute unit          */
-    int32_t unroll; /* float4 groups loaded per lane per step: 1, 2 or 4     */
+    int32_t grid;   /* persistent workgroups; 0: 2 per compute unit          */
+    int32_t unroll; /* float4 groups per lane per step: 1, 2, 4, 8 (0: 2)   */
 } ff_dot_cfg;
 
 /* Bytes of device workspace ff_dot_batched / ff_dot_ff_batched need for
@@ -201,7 +202,7 @@ ff_status ff_sum_ff_batched(const float *x_hi, const float *x_lo,
                             void *stream);
 
 /* Launch-shape autotuner for ff_dot_batched on this batch: times every
- * candidate (block 256/512 x unroll 1/2/4 x chunk 4096..65536 x 2..16
+ * candidate (block 256/512 x unroll 1/2/4/8 x chunk 4096..65536 x 2..16
  * workgroups per compute unit) whose workspace fits in ws_bytes, `reps`
  * launches each after one untimed launch, with HIP events on `stream`, and
  * returns the fastest in *best with its mean time in *best_ms.  SYNCHRONOUS:

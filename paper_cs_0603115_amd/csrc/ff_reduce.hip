@@ -1,22 +1,26 @@
-// ff_reduce.hip -- batched float-float dot products in one persistent launch.
+// ff_reduce.hip -- batched float-float dot products and sums.
 //
 // Data: vector v is [offsets[v], offsets[v+1]) of the concatenated inputs
 // (binary32 x, y, or float-float planes xh, xl, yh, yl).  A vector is cut
-// into chunks of `chunk` elements; chunk c of the whole batch is reduced by
-// one workgroup into a float-float partial in the workspace, and the
-// workgroup that finishes a vector's last chunk (completion counter per
-// vector) combines that vector's partials.
+// into chunks of `chunk` elements.  Four stream-ordered launches:
+//   plan      one workgroup: chunk counts per vector and their exclusive scan
+//   records   one wavefront per vector: the element range of each chunk
+//   partials  persistent: chunk c is reduced by workgroup c mod grid into a
+//             float-float partial
+//   combine   one wavefront per vector: Add22 of the vector's partials
+// Launch boundaries order the phases, so no fences or atomics are needed: a
+// device-scope fence on gfx950 writes back and invalidates the L2 of the
+// issuing XCD, which per chunk cost more than the chunk's own traffic.
 //
 // Per element the binary32 path reads 8 bytes and performs TwoProd (2 VALU)
 // plus Add22 (~14 VALU): ~2 operations per byte, under the ~4.9 ops/byte
 // ridge of gfx950 (39.3 T lane-ops/s unpacked FP32 over 8 TB/s), so the
-// kernel is HBM-bound.  The float-float path reads 16 bytes and performs
-// Mul22 + Add22 (~27 VALU) per element.
+// partials launch is HBM-bound.  The float-float path reads 16 bytes and
+// performs Mul22 + Add22 (~27 VALU) per element.
 //
 // Workspace layout (each section 256-byte aligned):
 //   chunk_start int64[nvec + 1]  first chunk of each vector (exclusive scan)
-//   chunk_vec   int32[cap]       owning vector of each chunk
-//   counters    uint32[nvec]     chunks of the vector finished so far
+//   ranges      int64x2[cap]     element range [s, e) of each chunk
 //   partials    float2[cap]      float-float partial of each chunk
 // with cap = total_len / chunk + nvec chunks at most.
 #include "ff_device.h"
@@ -30,8 +34,7 @@ constexpr int kPlanBlock = 1024;
 
 struct Workspace {
     int64_t *chunk_start;
-    int32_t *chunk_vec;
-    uint32_t *counters;
+    longlong2 *ranges;
     float2 *partials;
     int64_t cap;
 };
@@ -46,8 +49,8 @@ inline int64_t chunk_capacity(int64_t total, int32_t nvec, int64_t chunk)
 inline size_t workspace_bytes(int64_t total, int32_t nvec, int64_t chunk)
 {
     const int64_t cap = chunk_capacity(total, nvec, chunk);
-    return align256(sizeof(int64_t) * (nvec + 1)) + align256(sizeof(int32_t) * cap) +
-           align256(sizeof(uint32_t) * nvec) + align256(sizeof(float2) * cap);
+    return align256(sizeof(int64_t) * (nvec + 1)) + align256(sizeof(longlong2) * cap) +
+           align256(sizeof(float2) * cap);
 }
 
 inline Workspace carve(void *ws, int64_t total, int32_t nvec, int64_t chunk)
@@ -57,10 +60,8 @@ inline Workspace carve(void *ws, int64_t total, int32_t nvec, int64_t chunk)
     w.cap = chunk_capacity(total, nvec, chunk);
     w.chunk_start = reinterpret_cast<int64_t *>(p);
     p += align256(sizeof(int64_t) * (nvec + 1));
-    w.chunk_vec = reinterpret_cast<int32_t *>(p);
-    p += align256(sizeof(int32_t) * w.cap);
-    w.counters = reinterpret_cast<uint32_t *>(p);
-    p += align256(sizeof(uint32_t) * nvec);
+    w.ranges = reinterpret_cast<longlong2 *>(p);
+    p += align256(sizeof(longlong2) * w.cap);
     w.partials = reinterpret_cast<float2 *>(p);
     return w;
 }
@@ -70,13 +71,11 @@ __device__ __forceinline__ int64_t clamp_offset(int64_t o, int64_t total)
     return o < 0 ? 0 : (o > total ? total : o);
 }
 
-// Planning launch (one workgroup): chunk counts, their exclusive scan,
-// the chunk -> vector map, zeroed completion counters, and (0, 0) for empty
-// vectors.  Chunks beyond the workspace capacity are never mapped.
+// Planning launch (one workgroup): chunk counts of the vectors and their
+// exclusive scan.
 __global__ __launch_bounds__(kPlanBlock) void dot_plan(const int64_t *__restrict__ offsets,
                                                        int32_t nvec, int64_t total, int64_t chunk,
-                                                       Workspace w, float *__restrict__ out_hi,
-                                                       float *__restrict__ out_lo)
+                                                       Workspace w)
 {
     __shared__ int64_t scan[kPlanBlock];
     __shared__ int64_t carry;
@@ -92,11 +91,6 @@ __global__ __launch_bounds__(kPlanBlock) void dot_plan(const int64_t *__restrict
             const int64_t e = clamp_offset(offsets[v + 1], total);
             const int64_t len = e > b ? e - b : 0;
             n = (len + chunk - 1) / chunk;
-            w.counters[v] = 0u;
-            if (len == 0) {
-                out_hi[v] = 0.0f;
-                out_lo[v] = 0.0f;
-            }
         }
         scan[tid] = n;
         __syncthreads();
@@ -115,31 +109,70 @@ __global__ __launch_bounds__(kPlanBlock) void dot_plan(const int64_t *__restrict
     }
     if (tid == 0)
         w.chunk_start[nvec] = carry;
-    __syncthreads();
-    for (int64_t v = tid; v < nvec; v += kPlanBlock) {
-        const int64_t c1 = w.chunk_start[v + 1] < w.cap ? w.chunk_start[v + 1] : w.cap;
-        for (int64_t c = w.chunk_start[v]; c < c1; ++c)
-            w.chunk_vec[c] = static_cast<int32_t>(v);
+}
+
+// One wavefront per vector writes the element ranges of its chunks.
+// Chunks beyond the workspace capacity are never recorded.
+__global__ __launch_bounds__(256) void dot_ranges(const int64_t *__restrict__ offsets,
+                                                  int32_t nvec, int64_t total, int64_t chunk,
+                                                  Workspace w)
+{
+    const int64_t v = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (v >= nvec)
+        return;
+    const int64_t vb = clamp_offset(offsets[v], total);
+    const int64_t ve = clamp_offset(offsets[v + 1], total);
+    const int64_t c0 = w.chunk_start[v];
+    int64_t c1 = w.chunk_start[v + 1];
+    c1 = c1 < w.cap ? c1 : w.cap;
+    for (int64_t c = c0 + lane; c < c1; c += 64) {
+        const int64_t rs = vb + (c - c0) * chunk;
+        const int64_t re = ve < rs + chunk ? ve : rs + chunk;
+        w.ranges[c] = make_longlong2(rs, re);
     }
 }
 
-// Input kinds.  load4() returns the four terms of the float4 group starting
-// at element 4*g as exact float-float products; lanes outside [s, e) give 0.
+// One wavefront per vector: Add22 of the vector's chunk partials, lane-
+// strided in chunk order, then a butterfly; (0, 0) for an empty vector.
+__global__ __launch_bounds__(256) void dot_combine(int32_t nvec, Workspace w,
+                                                   float *__restrict__ out_hi,
+                                                   float *__restrict__ out_lo)
+{
+    const int64_t v = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (v >= nvec)
+        return;
+    const int64_t c0 = w.chunk_start[v];
+    int64_t c1 = w.chunk_start[v + 1];
+    c1 = c1 < w.cap ? c1 : w.cap;
+    float h = 0.0f, l = 0.0f;
+    for (int64_t c = c0 + lane; c < c1; c += 64) {
+        const float2 p = w.partials[c];
+        ffd::add22(h, l, p.x, p.y, h, l);
+    }
+    ffd::wave_allreduce_add22(h, l);
+    if (lane == 0) {
+        out_hi[v] = h;
+        out_lo[v] = l;
+    }
+}
+
+// Input kinds.  Terms<In> loads the float4 group g (elements 4g .. 4g+3)
+// of every input plane into a Group, and adds its four exact terms to four
+// float-float accumulators; the masked form zeroes the terms whose element
+// lies outside [s, e) (a zero term leaves an Add22 accumulator unchanged).
 struct InF32 {
     const float *x, *y;
-    static constexpr int kBytes = 8;
 };
 struct InFF {
     const float *xh, *xl, *yh, *yl;
-    static constexpr int kBytes = 16;
 };
 struct InSumF32 {
     const float *x;
-    static constexpr int kBytes = 4;
 };
 struct InSumFF {
     const float *xh, *xl;
-    static constexpr int kBytes = 8;
 };
 
 __device__ __forceinline__ void accumulate_term(float &h, float &l, float ph, float pl)
@@ -147,152 +180,117 @@ __device__ __forceinline__ void accumulate_term(float &h, float &l, float ph, fl
     ffd::add22(h, l, ph, pl, h, l);
 }
 
+template <int P>
+struct Planes {
+    f32x4 p[P];
+};
+
+__device__ __forceinline__ f32x4 load_group(const float *a, int64_t g)
+{
+    return __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(a) + g);
+}
+
 template <class In>
 struct Terms;
 
 template <>
 struct Terms<InF32> {
-    // Four terms of group g (elements 4g..4g+3), masked to [s, e).
-    __device__ __forceinline__ static void group(const InF32 &in, int64_t g, int64_t s, int64_t e,
-                                                 int64_t total, float2 acc[4])
+    using G = Planes<2>;
+    __device__ __forceinline__ static G load(const InF32 &in, int64_t g)
     {
-        const int64_t i0 = 4 * g;
-        f32x4 x, y;
-        if (i0 + 4 <= total) {
-            x = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(in.x) + g);
-            y = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(in.y) + g);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                x[k] = i0 + k < total ? in.x[i0 + k] : 0.0f;
-                y[k] = i0 + k < total ? in.y[i0 + k] : 0.0f;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            // both factors zeroed outside [s, e): the term is then exactly 0
-            // and Add22 leaves the accumulator unchanged
-            const bool on = (i0 + k >= s) && (i0 + k < e);
-            float p, q;
-            ffd::mul12_fma(on ? x[k] : 0.0f, on ? y[k] : 0.0f, p, q);
-            accumulate_term(acc[k].x, acc[k].y, p, q);
-        }
+        return G{{load_group(in.x, g), load_group(in.y, g)}};
     }
-    __device__ __forceinline__ static void one(const InF32 &in, int64_t i, float2 &acc)
+    __device__ __forceinline__ static void term(const G &q, int k, float &ph, float &pl)
     {
-        float p, q;
-        ffd::mul12_fma(in.x[i], in.y[i], p, q);
-        accumulate_term(acc.x, acc.y, p, q);
+        ffd::mul12_fma(q.p[0][k], q.p[1][k], ph, pl);
+    }
+    __device__ __forceinline__ static void one(const InF32 &in, int64_t i, float &ph, float &pl)
+    {
+        ffd::mul12_fma(in.x[i], in.y[i], ph, pl);
     }
 };
 
 template <>
 struct Terms<InFF> {
-    __device__ __forceinline__ static void group(const InFF &in, int64_t g, int64_t s, int64_t e,
-                                                 int64_t total, float2 acc[4])
+    using G = Planes<4>;
+    __device__ __forceinline__ static G load(const InFF &in, int64_t g)
     {
-        const int64_t i0 = 4 * g;
-        f32x4 xh, xl, yh, yl;
-        if (i0 + 4 <= total) {
-            xh = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(in.xh) + g);
-            xl = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(in.xl) + g);
-            yh = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(in.yh) + g);
-            yl = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(in.yl) + g);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const bool in_range = i0 + k < total;
-                xh[k] = in_range ? in.xh[i0 + k] : 0.0f;
-                xl[k] = in_range ? in.xl[i0 + k] : 0.0f;
-                yh[k] = in_range ? in.yh[i0 + k] : 0.0f;
-                yl[k] = in_range ? in.yl[i0 + k] : 0.0f;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const bool on = (i0 + k >= s) && (i0 + k < e);
-            float ph, pl;
-            ffd::mul22<false>(on ? xh[k] : 0.0f, on ? xl[k] : 0.0f, on ? yh[k] : 0.0f,
-                              on ? yl[k] : 0.0f, ph, pl);
-            accumulate_term(acc[k].x, acc[k].y, ph, pl);
-        }
+        return G{{load_group(in.xh, g), load_group(in.xl, g), load_group(in.yh, g),
+                  load_group(in.yl, g)}};
     }
-    __device__ __forceinline__ static void one(const InFF &in, int64_t i, float2 &acc)
+    __device__ __forceinline__ static void term(const G &q, int k, float &ph, float &pl)
     {
-        float ph, pl;
+        ffd::mul22<false>(q.p[0][k], q.p[1][k], q.p[2][k], q.p[3][k], ph, pl);
+    }
+    __device__ __forceinline__ static void one(const InFF &in, int64_t i, float &ph, float &pl)
+    {
         ffd::mul22<false>(in.xh[i], in.xl[i], in.yh[i], in.yl[i], ph, pl);
-        accumulate_term(acc.x, acc.y, ph, pl);
     }
 };
 
 template <>
 struct Terms<InSumF32> {
-    // term = (x_i, 0): the binary32 value itself
-    __device__ __forceinline__ static void group(const InSumF32 &in, int64_t g, int64_t s,
-                                                 int64_t e, int64_t total, float2 acc[4])
+    using G = Planes<1>;
+    __device__ __forceinline__ static G load(const InSumF32 &in, int64_t g)
     {
-        const int64_t i0 = 4 * g;
-        f32x4 x;
-        if (i0 + 4 <= total) {
-            x = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(in.x) + g);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                x[k] = i0 + k < total ? in.x[i0 + k] : 0.0f;
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const bool on = (i0 + k >= s) && (i0 + k < e);
-            accumulate_term(acc[k].x, acc[k].y, on ? x[k] : 0.0f, 0.0f);
-        }
+        return G{{load_group(in.x, g)}};
     }
-    __device__ __forceinline__ static void one(const InSumF32 &in, int64_t i, float2 &acc)
+    // term = (x_i, 0): the binary32 value itself
+    __device__ __forceinline__ static void term(const G &q, int k, float &ph, float &pl)
     {
-        accumulate_term(acc.x, acc.y, in.x[i], 0.0f);
+        ph = q.p[0][k];
+        pl = 0.0f;
+    }
+    __device__ __forceinline__ static void one(const InSumF32 &in, int64_t i, float &ph,
+                                               float &pl)
+    {
+        ph = in.x[i];
+        pl = 0.0f;
     }
 };
 
 template <>
 struct Terms<InSumFF> {
-    __device__ __forceinline__ static void group(const InSumFF &in, int64_t g, int64_t s,
-                                                 int64_t e, int64_t total, float2 acc[4])
+    using G = Planes<2>;
+    __device__ __forceinline__ static G load(const InSumFF &in, int64_t g)
     {
-        const int64_t i0 = 4 * g;
-        f32x4 xh, xl;
-        if (i0 + 4 <= total) {
-            xh = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(in.xh) + g);
-            xl = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(in.xl) + g);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const bool in_range = i0 + k < total;
-                xh[k] = in_range ? in.xh[i0 + k] : 0.0f;
-                xl[k] = in_range ? in.xl[i0 + k] : 0.0f;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const bool on = (i0 + k >= s) && (i0 + k < e);
-            accumulate_term(acc[k].x, acc[k].y, on ? xh[k] : 0.0f, on ? xl[k] : 0.0f);
-        }
+        return G{{load_group(in.xh, g), load_group(in.xl, g)}};
     }
-    __device__ __forceinline__ static void one(const InSumFF &in, int64_t i, float2 &acc)
+    __device__ __forceinline__ static void term(const G &q, int k, float &ph, float &pl)
     {
-        accumulate_term(acc.x, acc.y, in.xh[i], in.xl[i]);
+        ph = q.p[0][k];
+        pl = q.p[1][k];
+    }
+    __device__ __forceinline__ static void one(const InSumFF &in, int64_t i, float &ph,
+                                               float &pl)
+    {
+        ph = in.xh[i];
+        pl = in.xl[i];
     }
 };
 
-// The persistent launch.  Chunk c goes to workgroup c mod gridDim.x.
-// VEC: all planes 16-byte aligned, float4 groups; otherwise element loads.
+template <class In>
+__device__ __forceinline__ void add_group(const typename Terms<In>::G &q, float2 acc[4])
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        float ph, pl;
+        Terms<In>::term(q, k, ph, pl);
+        accumulate_term(acc[k].x, acc[k].y, ph, pl);
+    }
+}
+
+// The persistent partials launch.  Chunk c goes to workgroup c mod gridDim.x.
+// VEC (all planes 16-byte aligned): the float4 groups lying wholly inside
+// the chunk are read UNROLL at a time per lane, all loads issued before any
+// arithmetic; the at most 3 + 3 elements before the first and after the
+// last whole group are read one by one.  Otherwise every element is read
+// on its own.
 template <class In, int BLOCK, int UNROLL, bool VEC>
-__global__ __launch_bounds__(BLOCK) void dot_batched(In in, const int64_t *__restrict__ offsets,
-                                                     int64_t total, int64_t chunk, Workspace w,
-                                                     int32_t nvec, float *__restrict__ out_hi,
-                                                     float *__restrict__ out_lo)
+__global__ __launch_bounds__(BLOCK) void dot_partials(In in, Workspace w, int32_t nvec)
 {
     constexpr int kWaves = BLOCK / 64;
     __shared__ float2 wave_part[kWaves];
-    __shared__ int last_flag;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -301,32 +299,52 @@ __global__ __launch_bounds__(BLOCK) void dot_batched(In in, const int64_t *__res
         nchunks = w.cap;
 
     for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        const int v = w.chunk_vec[c];
-        const int64_t vb = clamp_offset(offsets[v], total);
-        const int64_t ve = clamp_offset(offsets[v + 1], total);
-        const int64_t c0 = w.chunk_start[v];
-        const int64_t c1 = w.chunk_start[v + 1];
-        const int64_t s = vb + (c - c0) * chunk;
-        const int64_t e = (ve < s + chunk) ? ve : s + chunk;
+        const longlong2 r = w.ranges[c];
+        const int64_t s = r.x, e = r.y;
 
         float2 acc[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             acc[k] = make_float2(0.0f, 0.0f);
         if (VEC) {
-            const int64_t g0 = s >> 2;
-            const int64_t g1 = (e + 3) >> 2;
-            for (int64_t g = g0 + tid; g < g1; g += BLOCK * UNROLL) {
+            const int64_t ga = (s + 3) >> 2;   // first whole group
+            int64_t gb = e >> 2;               // end of the whole groups
+            if (gb < ga)
+                gb = ga;                       // s and e inside one group
+            const int64_t gstep = static_cast<int64_t>(BLOCK) * UNROLL;
+            int64_t g = ga + tid;
+            for (; g + (UNROLL - 1) * BLOCK < gb; g += gstep) {
+                typename Terms<In>::G q[UNROLL];
 #pragma unroll
-                for (int u = 0; u < UNROLL; ++u) {
-                    const int64_t gu = g + u * BLOCK;
-                    if (gu < g1)
-                        Terms<In>::group(in, gu, s, e, total, acc);
-                }
+                for (int u = 0; u < UNROLL; ++u)
+                    q[u] = Terms<In>::load(in, g + u * BLOCK);
+#pragma unroll
+                for (int u = 0; u < UNROLL; ++u)
+                    add_group<In>(q[u], acc);
+            }
+            for (; g < gb; g += BLOCK)
+                add_group<In>(Terms<In>::load(in, g), acc);
+            // head [s, 4 ga) and tail [4 gb, e) elements, by threads 0..2
+            // and 64..66 (when a chunk lies inside one group, gb = ga and
+            // the head covers it)
+            const int64_t head_end = 4 * ga < e ? 4 * ga : e;
+            const int64_t tail_beg = 4 * gb > s ? 4 * gb : s;
+            int64_t i = -1;
+            if (tid < 3 && s + tid < head_end)
+                i = s + tid;
+            else if (tid >= 64 && tid < 67 && tail_beg + (tid - 64) < e && tail_beg >= head_end)
+                i = tail_beg + (tid - 64);
+            if (i >= 0) {
+                float ph, pl;
+                Terms<In>::one(in, i, ph, pl);
+                accumulate_term(acc[0].x, acc[0].y, ph, pl);
             }
         } else {
-            for (int64_t i = s + tid; i < e; i += BLOCK)
-                Terms<In>::one(in, i, acc[0]);
+            for (int64_t i = s + tid; i < e; i += BLOCK) {
+                float ph, pl;
+                Terms<In>::one(in, i, ph, pl);
+                accumulate_term(acc[0].x, acc[0].y, ph, pl);
+            }
         }
         float h = acc[0].x, l = acc[0].y;
         ffd::add22(h, l, acc[1].x, acc[1].y, h, l);
@@ -343,23 +361,6 @@ __global__ __launch_bounds__(BLOCK) void dot_batched(In in, const int64_t *__res
             for (int k = 1; k < kWaves; ++k)
                 ffd::add22(th, tl, wave_part[k].x, wave_part[k].y, th, tl);
             w.partials[c] = make_float2(th, tl);
-            __threadfence();   // publish the partial before counting it
-            const uint32_t done = atomicAdd(&w.counters[v], 1u);
-            last_flag = (static_cast<int64_t>(done) == c1 - c0 - 1);
-        }
-        __syncthreads();
-        if (last_flag && wave == 0) {
-            __threadfence();   // observe the other workgroups' partials
-            float ph = 0.0f, pl = 0.0f;
-            for (int64_t k = c0 + lane; k < c1; k += 64) {
-                const float2 p = w.partials[k];
-                ffd::add22(ph, pl, p.x, p.y, ph, pl);
-            }
-            ffd::wave_allreduce_add22(ph, pl);
-            if (lane == 0) {
-                out_hi[v] = ph;
-                out_lo[v] = pl;
-            }
         }
         __syncthreads();
     }
@@ -372,7 +373,8 @@ struct Cfg {
 
 ff_status resolve_cfg(const ff_dot_cfg *cfg, Cfg &out)
 {
-    out.block = 256;
+    // defaults: the fastest shape on 4096 vectors of 2^6 .. 2^20 elements
+    out.block = 512;
     out.chunk = 16384;
     out.grid = 0;
     out.unroll = 2;
@@ -388,7 +390,7 @@ ff_status resolve_cfg(const ff_dot_cfg *cfg, Cfg &out)
     }
     if (out.block != 256 && out.block != 512)
         return FF_ERR_ARG;
-    if (out.unroll != 1 && out.unroll != 2 && out.unroll != 4)
+    if (out.unroll != 1 && out.unroll != 2 && out.unroll != 4 && out.unroll != 8)
         return FF_ERR_ARG;
     if (out.chunk < 64 || out.chunk % 4 != 0)
         return FF_ERR_ARG;
@@ -402,20 +404,19 @@ int default_grid()
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    return 8 * (cus > 0 ? cus : 256);
+    return 2 * (cus > 0 ? cus : 256);
 }
 
 template <class In, int BLOCK, int UNROLL>
-void launch_main(bool vec, int grid, hipStream_t st, const In &in, const int64_t *offsets,
-                 int64_t total, int64_t chunk, const Workspace &w, int32_t nvec, float *oh,
-                 float *ol)
+void launch_partials(bool vec, int grid, hipStream_t st, const In &in, const Workspace &w,
+                     int32_t nvec)
 {
     if (vec)
-        hipLaunchKernelGGL((dot_batched<In, BLOCK, UNROLL, true>), dim3(grid), dim3(BLOCK), 0, st,
-                           in, offsets, total, chunk, w, nvec, oh, ol);
+        hipLaunchKernelGGL((dot_partials<In, BLOCK, UNROLL, true>), dim3(grid), dim3(BLOCK), 0,
+                           st, in, w, nvec);
     else
-        hipLaunchKernelGGL((dot_batched<In, BLOCK, 1, false>), dim3(grid), dim3(BLOCK), 0, st, in,
-                           offsets, total, chunk, w, nvec, oh, ol);
+        hipLaunchKernelGGL((dot_partials<In, BLOCK, 1, false>), dim3(grid), dim3(BLOCK), 0, st,
+                           in, w, nvec);
 }
 
 template <class In>
@@ -439,23 +440,29 @@ ff_status dot_batched_entry(const In &in, bool vec, const int64_t *offsets, int3
     hipStream_t st = ffh::as_stream(stream_ptr);
     const Workspace w = carve(ws, total, nvec, cfg.chunk);
     const int grid = cfg.grid ? cfg.grid : default_grid();
-    hipLaunchKernelGGL(dot_plan, dim3(1), dim3(kPlanBlock), 0, st, offsets, nvec, total, cfg.chunk,
-                       w, out_hi, out_lo);
+    const unsigned wave_blocks = static_cast<unsigned>(ffh::cdiv(nvec, 4));
+    hipLaunchKernelGGL(dot_plan, dim3(1), dim3(kPlanBlock), 0, st, offsets, nvec, total,
+                       cfg.chunk, w);
+    hipLaunchKernelGGL(dot_ranges, dim3(wave_blocks), dim3(256), 0, st, offsets, nvec, total,
+                       cfg.chunk, w);
+#define FF_DOT_LAUNCH(B, U) launch_partials<In, B, U>(vec, grid, st, in, w, nvec)
     if (cfg.block == 256) {
-        if (cfg.unroll == 1)
-            launch_main<In, 256, 1>(vec, grid, st, in, offsets, total, cfg.chunk, w, nvec, out_hi, out_lo);
-        else if (cfg.unroll == 2)
-            launch_main<In, 256, 2>(vec, grid, st, in, offsets, total, cfg.chunk, w, nvec, out_hi, out_lo);
-        else
-            launch_main<In, 256, 4>(vec, grid, st, in, offsets, total, cfg.chunk, w, nvec, out_hi, out_lo);
+        switch (cfg.unroll) {
+        case 1: FF_DOT_LAUNCH(256, 1); break;
+        case 2: FF_DOT_LAUNCH(256, 2); break;
+        case 4: FF_DOT_LAUNCH(256, 4); break;
+        default: FF_DOT_LAUNCH(256, 8); break;
+        }
     } else {
-        if (cfg.unroll == 1)
-            launch_main<In, 512, 1>(vec, grid, st, in, offsets, total, cfg.chunk, w, nvec, out_hi, out_lo);
-        else if (cfg.unroll == 2)
-            launch_main<In, 512, 2>(vec, grid, st, in, offsets, total, cfg.chunk, w, nvec, out_hi, out_lo);
-        else
-            launch_main<In, 512, 4>(vec, grid, st, in, offsets, total, cfg.chunk, w, nvec, out_hi, out_lo);
+        switch (cfg.unroll) {
+        case 1: FF_DOT_LAUNCH(512, 1); break;
+        case 2: FF_DOT_LAUNCH(512, 2); break;
+        case 4: FF_DOT_LAUNCH(512, 4); break;
+        default: FF_DOT_LAUNCH(512, 8); break;
+        }
     }
+#undef FF_DOT_LAUNCH
+    hipLaunchKernelGGL(dot_combine, dim3(wave_blocks), dim3(256), 0, st, nvec, w, out_hi, out_lo);
     return ffh::launch_status();
 }
 
@@ -551,7 +558,7 @@ ff_status ff_dot_batched_autotune(const float *x, const float *y, const int64_t 
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return ffh::hip_failure(hipGetLastError());
     static const int kBlocks[] = {256, 512};
-    static const int kUnrolls[] = {1, 2, 4};
+    static const int kUnrolls[] = {1, 2, 4, 8};
     static const int kChunks[] = {4096, 8192, 16384, 32768, 65536};
     static const int kPerCu[] = {2, 4, 8, 16};
     hipStream_t st = ffh::as_stream(stream);

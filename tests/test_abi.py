@@ -119,7 +119,7 @@ def test_dot_workspace_size():
     assert size(0, 0) > 0 or size(0, 0) == 0
     assert size(1 << 20, 10) > 0
     assert size(-1, 10) == 0 and size(10, -1) == 0
-    assert size(100, 3, (0, 0, 0, 3)) == 0          # unroll must be 1, 2 or 4
+    assert size(100, 3, (0, 0, 0, 3)) == 0          # unroll must be 1, 2, 4 or 8
     assert size(100, 3, (0, 60, 0, 0)) == 0         # chunk >= 64
     assert size(100, 3, (0, 66, 0, 0)) == 0         # chunk multiple of 4
     assert size(100, 3, (128, 0, 0, 0)) == 0        # block 256 or 512
