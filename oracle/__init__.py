@@ -52,6 +52,7 @@ _F = ctypes.POINTER(ctypes.c_float)
 _I64 = ctypes.POINTER(ctypes.c_int64)
 _i64 = ctypes.c_int64
 _int = ctypes.c_int
+_D = ctypes.POINTER(ctypes.c_double)
 
 _SIGS = {
     "oracle_abi_version": ([], _int),
@@ -70,6 +71,8 @@ _SIGS = {
     "oracle_dot_ff_seq": ([_F, _F, _i64, _F, _F, _i64, _i64, _F], None),
     "oracle_gemm_ff_seq": ([_i64, _F, _F, _i64, _F, _F, _i64, _F, _F, _i64,
                             _i64, _i64, _i64, _i64], None),
+    "oracle_f32_ref": ([_int, _F, _F, _F, _F, _i64], _int),
+    "oracle_ff_errors": ([_int, _F, _F, _F, _F, _F, _F, _i64, _D, _D], _int),
     "oracle_exact_dot": ([_F, _i64, _F, _i64, _i64, _I64], None),
     "oracle_exact_dot_ff": ([_F, _F, _i64, _F, _F, _i64, _i64, _I64], None),
     "oracle_exact_dot_batched": ([_F, _F, _I64, _i64, _I64], None),
@@ -124,6 +127,8 @@ def _p(a: np.ndarray):
         return a.ctypes.data_as(_F)
     if a.dtype == np.int64:
         return a.ctypes.data_as(_I64)
+    if a.dtype == np.float64:
+        return a.ctypes.data_as(_D)
     raise TypeError(a.dtype)
 
 
@@ -211,6 +216,38 @@ def elementwise(op: str, ah, al, bh, bl, out=None):
     if rc != 0:
         raise ValueError(op)
     return rh, rl
+
+
+F32_REF_OPS = {"add": 0, "mul": 1, "mad": 2}
+
+
+def f32_ref(op: str, a, b, c=None):
+    """The binary32 reference operators of the paper's timing tables
+    (section 6): 'add' a (+) b, 'mul' a (x) b, 'mad' fma(a, b, c)."""
+    if c is None:
+        c = np.zeros_like(_f32(a))
+    (a, b, c), n = _pair_inputs(a, b, c)
+    r = np.empty(n, np.float32)
+    if lib().oracle_f32_ref(F32_REF_OPS[op], _p(a), _p(b), _p(c), _p(r), n) != 0:
+        raise ValueError(op)
+    return r
+
+
+FF_ERROR_OPS = {"add22": 0, "mul22": 1, "add12": 2, "mul12": 3}
+
+
+def ff_errors(op: str, ah, al, bh, bl, rh, rl):
+    """Exact errors of results (rh, rl) of an operator on (ah, al), (bh, bl)
+    (section 6.1): returns (rel, ratio), binary64 arrays with
+    rel = |err| / |exact| and ratio = |err| / (the theorem's bound).  For
+    'add12' and 'mul12' the low inputs are ignored and the bound is 0 (the
+    results must be exact: ratio is +inf for any error)."""
+    (ah, al, bh, bl, rh, rl), n = _pair_inputs(ah, al, bh, bl, rh, rl)
+    rel, ratio = np.empty(n, np.float64), np.empty(n, np.float64)
+    if lib().oracle_ff_errors(FF_ERROR_OPS[op], _p(ah), _p(al), _p(bh), _p(bl), _p(rh), _p(rl),
+                              n, _p(rel), _p(ratio)) != 0:
+        raise ValueError(op)
+    return rel, ratio
 
 
 # --------------------------------------------------------------- reductions

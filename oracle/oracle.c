@@ -243,6 +243,30 @@ int oracle_elementwise(int op, const float *ah, const float *al,
     }
 }
 
+/* Binary32 reference operators, timed beside the float-float ones in the
+ * paper's tables (section 6, Tables 3 and 4): 0 add, 1 multiply, 2 multiply-
+ * add with a single rounding (fmaf).  Returns -1 for an unknown op. */
+int oracle_f32_ref(int op, const float *a, const float *b, const float *c,
+                   float *r, int64_t n)
+{
+    switch (op) {
+    case 0:
+        for (int64_t i = 0; i < n; ++i)
+            r[i] = a[i] + b[i];
+        return 0;
+    case 1:
+        for (int64_t i = 0; i < n; ++i)
+            r[i] = a[i] * b[i];
+        return 0;
+    case 2:
+        for (int64_t i = 0; i < n; ++i)
+            r[i] = fmaf(a[i], b[i], c[i]);
+        return 0;
+    default:
+        return -1;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Float-float accumulation in index order (reductions, matvec, plain GEMM) */
 /* ------------------------------------------------------------------------ */
@@ -440,6 +464,99 @@ void oracle_exact_gemm_entries(int64_t K, const float *Ah, const float *Al,
         oracle_exact_dot_ff(Ah + i * lda, Al + i * lda, 1, Bh + j, Bl + j, ldb,
                             K, limbs_out + t * LA_LIMBS);
     }
+}
+
+/* acc += sign * v for one binary32 value. */
+static void la_add_f32(long_acc *acc, float v, int sign)
+{
+    int64_t m;
+    int e;
+    f32_decompose(v, &m, &e);
+    la_add_scaled(acc, sign * m, e);
+}
+
+/* The accumulated value rounded to binary64 (for reporting errors only).
+ * The magnitude is summed limb by limb from the top, after the sign has been
+ * taken out, so that no cancellation occurs in the conversion. */
+static double la_to_double(long_acc *acc)
+{
+    la_normalise(acc);
+    int neg = acc->limb[LA_LIMBS - 1] < 0;
+    if (neg) {
+        for (int k = 0; k < LA_LIMBS; ++k)
+            acc->limb[k] = -acc->limb[k];
+        la_normalise(acc);
+    }
+    double v = 0.0;
+    for (int k = LA_LIMBS - 1; k >= 0; --k)
+        v += ldexp((double)acc->limb[k], 32 * k + LA_EMIN);
+    return neg ? -v : v;
+}
+
+/* Errors of operator results against the exact values: the measurement
+ * behind an accuracy table of the shape of Table 5 (section 6.1).  For each
+ * i, with E the exact result of the operation on the inputs:
+ *   op 0 Add22: E = ah + al + bh + bl, bound = max(2^-24 |al + bl|,
+ *               2^-44 |E|) (Add22 theorem)
+ *   op 1 Mul22: E = (ah + al)(bh + bl), bound = 2^-44 |E| (Mul22 theorem)
+ *   op 2 Add12: E = ah + bh (al, bl unused), bound = 0 (Add12 theorem: exact)
+ *   op 3 Mul12: E = ah * bh (al, bl unused), bound = 0 (Mul12 theorem: exact)
+ * The error err = (rh + rl) - E is formed without rounding; then
+ *   rel[i]   = |err| / |E|    (0 if err = 0; +inf if E = 0 != err)
+ *   ratio[i] = |err| / bound  (0 if err = 0; +inf if bound = 0 != err)
+ * rounded to binary64.  Returns -1 for an unknown op. */
+int oracle_ff_errors(int op, const float *ah, const float *al, const float *bh,
+                     const float *bl, const float *rh, const float *rl,
+                     int64_t n, double *rel, double *ratio)
+{
+    if (op < 0 || op > 3)
+        return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        long_acc exact, lo;
+        memset(&exact, 0, sizeof(exact));
+        memset(&lo, 0, sizeof(lo));
+        switch (op) {
+        case 0:
+            la_add_f32(&exact, ah[i], 1);
+            la_add_f32(&exact, al[i], 1);
+            la_add_f32(&exact, bh[i], 1);
+            la_add_f32(&exact, bl[i], 1);
+            la_add_f32(&lo, al[i], 1);
+            la_add_f32(&lo, bl[i], 1);
+            break;
+        case 1:
+            la_add_product(&exact, ah[i], bh[i]);
+            la_add_product(&exact, ah[i], bl[i]);
+            la_add_product(&exact, al[i], bh[i]);
+            la_add_product(&exact, al[i], bl[i]);
+            break;
+        case 2:
+            la_add_f32(&exact, ah[i], 1);
+            la_add_f32(&exact, bh[i], 1);
+            break;
+        default:
+            la_add_product(&exact, ah[i], bh[i]);
+            break;
+        }
+        long_acc err = exact;
+        for (int k = 0; k < LA_LIMBS; ++k)
+            err.limb[k] = -err.limb[k];
+        la_add_f32(&err, rh[i], 1);
+        la_add_f32(&err, rl[i], 1);
+        double e = fabs(la_to_double(&err));
+        double big = fabs(la_to_double(&exact));
+        double bound = 0.0;
+        if (op == 0) {
+            double lo_mag = fabs(la_to_double(&lo));
+            double b1 = ldexp(lo_mag, -24), b2 = ldexp(big, -44);
+            bound = b1 > b2 ? b1 : b2;
+        } else if (op == 1) {
+            bound = ldexp(big, -44);
+        }
+        rel[i] = e == 0.0 ? 0.0 : (big == 0.0 ? INFINITY : e / big);
+        ratio[i] = e == 0.0 ? 0.0 : (bound == 0.0 ? INFINITY : e / bound);
+    }
+    return 0;
 }
 
 /* Exact |A| |B| entries: sum_k |(Ah+Al)_ik| |(Bh+Bl)_kj|, the normwise scale

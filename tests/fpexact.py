@@ -78,3 +78,22 @@ def log2_abs(x: Fraction) -> float:
         return float("-inf")
     x = abs(x)
     return math.log2(x.numerator) - math.log2(x.denominator)
+
+
+def round_to_f32(q: Fraction) -> float:
+    """The binary32 value nearest to q, ties to even (subnormals included,
+    no overflow handling: |q| must stay below 2^128)."""
+    if q == 0:
+        return 0.0
+    sign = -1 if q < 0 else 1
+    q = abs(q)
+    e = q.numerator.bit_length() - q.denominator.bit_length()
+    if Fraction(2) ** e > q:
+        e -= 1                       # now 2^e <= q < 2^(e+1)
+    quantum = Fraction(2) ** (max(e, F32_MIN_NORMAL_EXP) - 23)
+    m = q / quantum
+    lo = m.numerator // m.denominator
+    rem = m - lo
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and lo % 2 == 1):
+        lo += 1
+    return sign * float(lo * quantum)

@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 import test_oracle_operators as OPS
+import test_oracle_paper_tables as TAB
 import test_oracle_primitives as PRIM
 import test_oracle_reductions as RED
 
@@ -42,6 +43,14 @@ RED_PINS = [
     RED.test_gemm_identity_returns_a,
     RED.test_gemm_block_and_exact_entries,
 ]
+TAB_PINS = [
+    lambda: TAB.test_f32_add_mul_match_numpy("add"),
+    lambda: TAB.test_f32_add_mul_match_numpy("mul"),
+    TAB.test_f32_mad_is_a_single_rounding,
+    lambda: TAB.test_ff_errors_against_fractions("add22"),
+    lambda: TAB.test_ff_errors_against_fractions("mul22"),
+    TAB.test_ff_errors_edge_cases,
+]
 
 # (name, original text, planted text, pins expected to catch it)
 MUTATIONS = [
@@ -69,6 +78,14 @@ MUTATIONS = [
     ("exact_exponent", "*e = ex - 24;", "*e = ex - 23;", RED_PINS),
     ("dot_dropped_error_term", "        add22(acc_h, acc_l, p, e, &acc_h, &acc_l);",
      "        add22(acc_h, acc_l, p, 0.0f, &acc_h, &acc_l);", RED_PINS),
+    ("mad_unfused", "r[i] = fmaf(a[i], b[i], c[i]);", "r[i] = a[i] * b[i] + c[i];",
+     TAB_PINS),
+    ("errors_dropped_low_word", "            la_add_f32(&exact, bl[i], 1);\n            la_add_f32(&lo, al[i], 1);",
+     "            la_add_f32(&lo, al[i], 1);", TAB_PINS),
+    ("errors_mul22_cross_term", "            la_add_product(&exact, al[i], bh[i]);\n            la_add_product(&exact, al[i], bl[i]);",
+     "            la_add_product(&exact, al[i], bh[i]);\n            la_add_product(&exact, al[i], bh[i]);", TAB_PINS),
+    ("errors_bound_exponent", "double b1 = ldexp(lo_mag, -24), b2 = ldexp(big, -44);",
+     "double b1 = ldexp(lo_mag, -24), b2 = ldexp(big, -45);", TAB_PINS),
     ("gemm_transposed_stride", "Bh + j, Bl + j,\n                              ldb, K, out);",
      "Bh + j, Bl + j,\n                              1, K, out);", RED_PINS),
 ]
