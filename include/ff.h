@@ -322,6 +322,42 @@ ff_status ff_gemm(int64_t M, int64_t N, int64_t K, const float *A_hi,
 /* Measurement probe                                                        */
 /* ------------------------------------------------------------------------ */
 
+/* ------------------------------------------------------------------------ */
+/* Error-free transforms and binary32 reference operators                   */
+/* ------------------------------------------------------------------------ */
+/*
+ * The building blocks the paper times beside its float-float operators
+ * (section 6, Tables 3 and 4), as stream operators over n binary32 elements
+ * with the same load/store pattern as the float-float operators:
+ *   ff_add12         (s_i, r_i) = Add12(a_i, b_i): s = a (+) b and
+ *                    r = (a + b) - s exactly (section 4.1, Add12 theorem;
+ *                    the branch-free six-operation form)
+ *   ff_mul12         (x_i, y_i): x = a (x) b, y = fma(a, b, -x), which is
+ *                    a*b - x exactly unless the error word underflows
+ *   ff_mul12_dekker  (x_i, y_i) = Mul12(a_i, b_i) through Split with the
+ *                    constant 4097 (section 4.1, Split and Mul12 theorems)
+ *   ff_f32_add       r_i = a_i (+) b_i           (the tables' "Add")
+ *   ff_f32_mul       r_i = a_i (x) b_i           (the tables' "Mul")
+ *   ff_f32_mad       r_i = fma(a_i, b_i, c_i), one rounding (the tables'
+ *                    "Mad"; gfx950 has no unfused binary32 multiply-add)
+ * All pointers: device, caller-owned, n binary32 words each; an output may
+ * alias an input exactly (in place), partial overlap is undefined.  When
+ * every pointer is 16-byte aligned the float4 path runs.
+ * Errors: FF_ERR_SIZE (n < 0), FF_ERR_NULL, FF_ERR_ALIGN (a pointer not
+ * 4-byte aligned), FF_ERR_HIP.  n = 0 is a no-op. */
+ff_status ff_add12(const float *a, const float *b, float *s, float *r,
+                   int64_t n, void *stream);
+ff_status ff_mul12(const float *a, const float *b, float *x, float *y,
+                   int64_t n, void *stream);
+ff_status ff_mul12_dekker(const float *a, const float *b, float *x, float *y,
+                          int64_t n, void *stream);
+ff_status ff_f32_add(const float *a, const float *b, float *r, int64_t n,
+                     void *stream);
+ff_status ff_f32_mul(const float *a, const float *b, float *r, int64_t n,
+                     void *stream);
+ff_status ff_f32_mad(const float *a, const float *b, const float *c, float *r,
+                     int64_t n, void *stream);
+
 /* dst[i] = src[i] for i < n (binary32), with the same load/store pattern as
  * the elementwise operators: the HBM bandwidth reference for roofline and
  * counter calibration.  Errors as for the elementwise operators. */

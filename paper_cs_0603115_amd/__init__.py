@@ -22,6 +22,7 @@ from ._lib import (GEMM_FMA_LOOP, GEMM_SLICED_BF16, GEMM_SLICED_I8, MATVEC_FAST,
 __all__ = [
     "lib", "FFError", "DotCfg", "build_info",
     "ff_add", "ff_sub", "ff_mul", "ff_mul_dekker", "ff_div", "ff_copy",
+    "ff_add12", "ff_mul12", "f32_add", "f32_mul", "f32_mad",
     "ff_dot_batched", "ff_dot_ff_batched", "ff_dot_batched_workspace_size",
     "ff_sum_batched", "ff_sum_ff_batched",
     "ff_matvec", "ff_matvec_backward", "ff_dot_backward", "MATVEC_FAST", "MATVEC_PLAIN",
@@ -125,6 +126,87 @@ def ff_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> torch.Tensor:
         check("ff_copy", lib.ff_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
                                      src.numel(), _stream_handle(stream)))
     return dst
+
+
+# ------------------------------------------- error-free transforms, binary32
+
+def _f32_operands(name: str, *ts: torch.Tensor):
+    for k, t in enumerate(ts):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float32:
+            raise TypeError(f"{name}: operand {k} must be a float32 tensor")
+        if not t.is_cuda:
+            raise ValueError(f"{name}: operands must be on a HIP device")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: operands must be contiguous")
+        if t.shape != ts[0].shape or t.device != ts[0].device:
+            raise ValueError(f"{name}: operands differ in shape or device")
+
+
+def _check_pair_out(name: str, out: torch.Tensor, a: torch.Tensor) -> None:
+    _check_ff(out, "out")
+    if out.shape != (2, *a.shape) or out.device != a.device:
+        raise ValueError(f"{name}: out must have shape {(2, *a.shape)} on {a.device}")
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def ff_add12(a: torch.Tensor, b: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    """Add12 theorem (section 4.1) elementwise on binary32 tensors: the
+    float-float result (s, r) with s = a (+) b and s + r = a + b exactly."""
+    _f32_operands("ff_add12", a, b)
+    out = ff_empty(a.shape, device=a.device) if out is None else out
+    _check_pair_out("ff_add12", out, a)
+    with torch.cuda.device(a.device):
+        check("ff_add12", lib.ff_add12(_ptr(a), _ptr(b), *_planes(out), a.numel(),
+                                       _stream_handle(stream)))
+    return out
+
+
+def ff_mul12(a: torch.Tensor, b: torch.Tensor, dekker: bool = False, out=None,
+             stream=None) -> torch.Tensor:
+    """Exact products elementwise: (x, y) with x = a (x) b, x + y = a b, by
+    FMA TwoProd or (dekker=True) by the Mul12 theorem's Split algorithm."""
+    name = "ff_mul12_dekker" if dekker else "ff_mul12"
+    _f32_operands(name, a, b)
+    out = ff_empty(a.shape, device=a.device) if out is None else out
+    _check_pair_out(name, out, a)
+    with torch.cuda.device(a.device):
+        check(name, getattr(lib, name)(_ptr(a), _ptr(b), *_planes(out), a.numel(),
+                                       _stream_handle(stream)))
+    return out
+
+
+def _f32_binary(name: str, a, b, out, stream) -> torch.Tensor:
+    _f32_operands(name, a, b)
+    out = torch.empty_like(a) if out is None else out
+    _f32_operands(name, a, out)
+    with torch.cuda.device(a.device):
+        check(name, getattr(lib, name)(_ptr(a), _ptr(b), _ptr(out), a.numel(),
+                                       _stream_handle(stream)))
+    return out
+
+
+def f32_add(a, b, out=None, stream=None) -> torch.Tensor:
+    """Binary32 a (+) b: the reference operator of the paper's tables."""
+    return _f32_binary("ff_f32_add", a, b, out, stream)
+
+
+def f32_mul(a, b, out=None, stream=None) -> torch.Tensor:
+    """Binary32 a (x) b: the reference operator of the paper's tables."""
+    return _f32_binary("ff_f32_mul", a, b, out, stream)
+
+
+def f32_mad(a, b, c, out=None, stream=None) -> torch.Tensor:
+    """Binary32 fma(a, b, c), one rounding: the tables' multiply-add."""
+    _f32_operands("ff_f32_mad", a, b, c)
+    out = torch.empty_like(a) if out is None else out
+    _f32_operands("ff_f32_mad", a, out)
+    with torch.cuda.device(a.device):
+        check("ff_f32_mad", lib.ff_f32_mad(_ptr(a), _ptr(b), _ptr(c), _ptr(out), a.numel(),
+                                           _stream_handle(stream)))
+    return out
 
 
 # ------------------------------------------------------------------ reductions

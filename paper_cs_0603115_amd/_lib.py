@@ -42,6 +42,12 @@ SIGNATURES = {
     "ff_mul_dekker": _EW,
     "ff_div": _EW,
     "ff_copy": ([_P, _P, _i64, _P], _st),
+    "ff_add12": ([_P, _P, _P, _P, _i64, _P], _st),
+    "ff_mul12": ([_P, _P, _P, _P, _i64, _P], _st),
+    "ff_mul12_dekker": ([_P, _P, _P, _P, _i64, _P], _st),
+    "ff_f32_add": ([_P, _P, _P, _i64, _P], _st),
+    "ff_f32_mul": ([_P, _P, _P, _i64, _P], _st),
+    "ff_f32_mad": ([_P, _P, _P, _P, _i64, _P], _st),
     "ff_dot_batched_workspace_size": ([_i64, _i32, ctypes.POINTER(DotCfg)], _sz),
     "ff_dot_batched": ([_P, _P, _P, _i32, _i64, ctypes.POINTER(DotCfg), _P, _sz, _P, _P, _P],
                        _st),

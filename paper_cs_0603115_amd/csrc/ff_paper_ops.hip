@@ -1,0 +1,198 @@
+// ff_paper_ops.hip -- the error-free transforms and binary32 reference
+// operators that the paper times beside its float-float operators (section
+// 6, Tables 3 and 4), as stream kernels over SoA planes:
+//   Add12 (section 4.1, Add12 theorem; the six-operation form),
+//   Mul12 with FMA TwoProd or with Dekker's Split (Mul12 theorem),
+//   binary32 add, multiply and multiply-add (one rounding).
+//
+// Same streaming structure as the float-float operators: 1024-thread
+// workgroups, one float4 group of every plane per thread, non-temporal
+// 16-byte loads and stores, a scalar kernel for the tail and for planes that
+// are not 16-byte aligned.  Bytes per element: 12 (add, mul), 16 (mad, Add12,
+// Mul12); all HBM-bound at large n, launch-bound at the paper's sizes.
+#include "ff_device.h"
+#include "ff_host.h"
+
+namespace ffk {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kStreamBlock = 1024;
+
+// An operator maps IN binary32 inputs of one element to OUT outputs.
+struct OpAdd12 {
+    static constexpr int kIn = 2, kOut = 2;
+    __device__ __forceinline__ static void apply(const float *x, float *y)
+    {
+        ffd::add12(x[0], x[1], y[0], y[1]);
+    }
+};
+struct OpMul12Fma {
+    static constexpr int kIn = 2, kOut = 2;
+    __device__ __forceinline__ static void apply(const float *x, float *y)
+    {
+        ffd::mul12_fma(x[0], x[1], y[0], y[1]);
+    }
+};
+struct OpMul12Dekker {
+    static constexpr int kIn = 2, kOut = 2;
+    __device__ __forceinline__ static void apply(const float *x, float *y)
+    {
+        ffd::mul12_dekker(x[0], x[1], y[0], y[1]);
+    }
+};
+struct OpF32Add {
+    static constexpr int kIn = 2, kOut = 1;
+    __device__ __forceinline__ static void apply(const float *x, float *y) { y[0] = x[0] + x[1]; }
+};
+struct OpF32Mul {
+    static constexpr int kIn = 2, kOut = 1;
+    __device__ __forceinline__ static void apply(const float *x, float *y) { y[0] = x[0] * x[1]; }
+};
+struct OpF32Mad {
+    static constexpr int kIn = 3, kOut = 1;
+    __device__ __forceinline__ static void apply(const float *x, float *y)
+    {
+        y[0] = __builtin_fmaf(x[0], x[1], x[2]);
+    }
+};
+
+template <int IN, int OUT>
+struct StreamPlanes {
+    const float *in[IN];
+    float *out[OUT];
+};
+
+template <class Op>
+__global__ __launch_bounds__(kStreamBlock) void stream_vec(StreamPlanes<Op::kIn, Op::kOut> p,
+                                                           int64_t nvec)
+{
+    const int64_t g = static_cast<int64_t>(blockIdx.x) * kStreamBlock + threadIdx.x;
+    if (g >= nvec)
+        return;
+    f32x4 x[Op::kIn], y[Op::kOut];
+#pragma unroll
+    for (int k = 0; k < Op::kIn; ++k)
+        x[k] = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p.in[k]) + g);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        float xi[Op::kIn], yo[Op::kOut];
+#pragma unroll
+        for (int k = 0; k < Op::kIn; ++k)
+            xi[k] = x[k][c];
+        Op::apply(xi, yo);
+#pragma unroll
+        for (int k = 0; k < Op::kOut; ++k)
+            y[k][c] = yo[k];
+    }
+#pragma unroll
+    for (int k = 0; k < Op::kOut; ++k)
+        __builtin_nontemporal_store(y[k], reinterpret_cast<f32x4 *>(p.out[k]) + g);
+}
+
+template <class Op>
+__global__ __launch_bounds__(kStreamBlock) void stream_scalar(StreamPlanes<Op::kIn, Op::kOut> p,
+                                                              int64_t n)
+{
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kStreamBlock;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kStreamBlock + threadIdx.x; i < n;
+         i += stride) {
+        float xi[Op::kIn], yo[Op::kOut];
+#pragma unroll
+        for (int k = 0; k < Op::kIn; ++k)
+            xi[k] = p.in[k][i];
+        Op::apply(xi, yo);
+#pragma unroll
+        for (int k = 0; k < Op::kOut; ++k)
+            p.out[k][i] = yo[k];
+    }
+}
+
+template <class Op>
+ff_status stream_op(StreamPlanes<Op::kIn, Op::kOut> p, int64_t n, void *stream_ptr)
+{
+    if (n < 0)
+        return FF_ERR_SIZE;
+    if (n == 0)
+        return FF_OK;
+    bool vec = true;
+    for (int k = 0; k < Op::kIn; ++k) {
+        if (!p.in[k])
+            return FF_ERR_NULL;
+        if (!ffh::aligned(p.in[k], 4))
+            return FF_ERR_ALIGN;
+        vec = vec && ffh::aligned(p.in[k], 16);
+    }
+    for (int k = 0; k < Op::kOut; ++k) {
+        if (!p.out[k])
+            return FF_ERR_NULL;
+        if (!ffh::aligned(p.out[k], 4))
+            return FF_ERR_ALIGN;
+        vec = vec && ffh::aligned(p.out[k], 16);
+    }
+    hipStream_t st = ffh::as_stream(stream_ptr);
+    int64_t done = 0;
+    if (vec) {
+        const int64_t nvec = n / 4;
+        done = 4 * nvec;
+        if (nvec > 0) {
+            const int64_t blocks = ffh::cdiv(nvec, kStreamBlock);
+            if (blocks > INT32_MAX)
+                return FF_ERR_SIZE;
+            hipLaunchKernelGGL(stream_vec<Op>, dim3(static_cast<unsigned>(blocks)),
+                               dim3(kStreamBlock), 0, st, p, nvec);
+        }
+    }
+    if (done < n) {
+        StreamPlanes<Op::kIn, Op::kOut> rest = p;
+        for (int k = 0; k < Op::kIn; ++k)
+            rest.in[k] += done;
+        for (int k = 0; k < Op::kOut; ++k)
+            rest.out[k] += done;
+        const int64_t blocks = ffh::cdiv(n - done, kStreamBlock);
+        hipLaunchKernelGGL(stream_scalar<Op>,
+                           dim3(static_cast<unsigned>(blocks < 65536 ? blocks : 65536)),
+                           dim3(kStreamBlock), 0, st, rest, n - done);
+    }
+    return ffh::launch_status();
+}
+
+} // namespace ffk
+
+using namespace ffk;
+
+extern "C" {
+
+ff_status ff_add12(const float *a, const float *b, float *s, float *r, int64_t n, void *stream)
+{
+    return stream_op<OpAdd12>(StreamPlanes<2, 2>{{a, b}, {s, r}}, n, stream);
+}
+
+ff_status ff_mul12(const float *a, const float *b, float *x, float *y, int64_t n, void *stream)
+{
+    return stream_op<OpMul12Fma>(StreamPlanes<2, 2>{{a, b}, {x, y}}, n, stream);
+}
+
+ff_status ff_mul12_dekker(const float *a, const float *b, float *x, float *y, int64_t n,
+                          void *stream)
+{
+    return stream_op<OpMul12Dekker>(StreamPlanes<2, 2>{{a, b}, {x, y}}, n, stream);
+}
+
+ff_status ff_f32_add(const float *a, const float *b, float *r, int64_t n, void *stream)
+{
+    return stream_op<OpF32Add>(StreamPlanes<2, 1>{{a, b}, {r}}, n, stream);
+}
+
+ff_status ff_f32_mul(const float *a, const float *b, float *r, int64_t n, void *stream)
+{
+    return stream_op<OpF32Mul>(StreamPlanes<2, 1>{{a, b}, {r}}, n, stream);
+}
+
+ff_status ff_f32_mad(const float *a, const float *b, const float *c, float *r, int64_t n,
+                     void *stream)
+{
+    return stream_op<OpF32Mad>(StreamPlanes<3, 1>{{a, b, c}, {r}}, n, stream);
+}
+
+} // extern "C"

@@ -90,6 +90,23 @@ def test_elementwise_validation(name):
         assert fn(*q, 10, None) == ERR_ALIGN
 
 
+@pytest.mark.parametrize("name,nptr", [("ff_add12", 4), ("ff_mul12", 4), ("ff_mul12_dekker", 4),
+                                       ("ff_f32_add", 3), ("ff_f32_mul", 3), ("ff_f32_mad", 4)])
+def test_stream_operator_validation(name, nptr):
+    fn = getattr(ff.lib, name)
+    p = [4096 * (k + 1) for k in range(nptr)]
+    assert fn(*p, -1, None) == ERR_SIZE
+    assert fn(*p, 0, None) == 0
+    assert fn(*([None] * nptr), 0, None) == 0
+    for k in range(nptr):
+        q = list(p)
+        q[k] = None
+        assert fn(*q, 10, None) == ERR_NULL
+        q = list(p)
+        q[k] = p[k] + 2
+        assert fn(*q, 10, None) == ERR_ALIGN
+
+
 def test_copy_validation():
     assert ff.lib.ff_copy(4096, 8192, -3, None) == ERR_SIZE
     assert ff.lib.ff_copy(4096, 8192, 0, None) == 0
