@@ -429,27 +429,77 @@ __device__ __forceinline__ uint8_t *lds_slot()
     return reinterpret_cast<uint8_t *>(slot);
 }
 
+// Epilogue of a wavefront's 32 x 32 block: lane holds
+// C[8*(r/4) + 4*(lane/32) + (r%4)][lane%32] for r = 0..15 as S diagonal sums;
+// T = sum_D S_D 256^(S-1-D) is formed exactly and rounded once to
+// float-float, then scaled by the row and column powers of two (and added
+// to C with Add22 for the later K-chunks).
+template <class Dg, int WM, int WN, class Acc>
+__device__ __forceinline__ void store_block(const Acc (&acc)[kS], const i32x16 (&iacc)[kS],
+                                            int64_t M, int64_t N, int bi, int bj, int wm, int wn,
+                                            int lane, const uint32_t *__restrict__ rowmax,
+                                            const uint32_t *__restrict__ colmax,
+                                            float *__restrict__ Ch, float *__restrict__ Cl,
+                                            int64_t ldc, int accumulate)
+{
+    const int64_t j = static_cast<int64_t>(bj) * (32 * WN) + wn * 32 + (lane & 31);
+    const int fj = j < N ? exponent_bound(colmax[j]) : 0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t i = static_cast<int64_t>(bi) * (32 * WM) + wm * 32 + m;
+        if (i >= M || j >= N)
+            continue;
+        __int128 T = 0;
+#pragma unroll
+        for (int d = 0; d < kS; ++d) {
+            int sd;
+            if constexpr (Dg::kExtractStages > 0)
+                sd = iacc[d][r];
+            else
+                sd = acc[d][r];
+            T = (T << 8) + static_cast<__int128>(sd);
+        }
+        float h, l;
+        i128_to_ff(T, exponent_bound(rowmax[i]) + fj + kEpiShift, h, l);
+        if (accumulate)
+            ffd::add22(Ch[i * ldc + j], Cl[i * ldc + j], h, l, h, l);
+        Ch[i * ldc + j] = h;
+        Cl[i * ldc + j] = l;
+    }
+}
+
 // Launch shape of the sliced product: WM x WN wavefronts (256 or 512
 // threads), each owning a 32 x 32 block of C as S diagonal accumulators, and
-// a ring of NST K-stages in LDS.
+// a ring of 3 K-stages in LDS (two in flight while one is consumed).
 template <class Dg> struct SlicedShape;
 // int8: 8 wavefronts (2 per SIMD, <= 256 registers each), 128 x 64 outputs,
-// 2 x 42 KiB stages.
+// 3 x 42 KiB stages.
 template <> struct SlicedShape<DigitsI8> {
-    static constexpr int WM = 4, WN = 2, NST = 2, WAVES_PER_SIMD = 2;
+    static constexpr int WM = 4, WN = 2, WAVES_PER_SIMD = 2;
 };
 // BF16: FP32 and int32 diagonal accumulators need ~400 registers, so one
-// wavefront per SIMD: 4 wavefronts, 64 x 64 outputs, 2 x 28 KiB stages.
+// wavefront per SIMD: 4 wavefronts, 64 x 64 outputs, 3 x 28 KiB stages.
 template <> struct SlicedShape<DigitsBF16> {
-    static constexpr int WM = 2, WN = 2, NST = 2, WAVES_PER_SIMD = 1;
+    static constexpr int WM = 2, WN = 2, WAVES_PER_SIMD = 1;
 };
+
+// s_waitcnt immediate that waits until at most n vector-memory operations of
+// this wavefront are outstanding (export and LDS counters left at maximum).
+constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+
+// Workgroup barrier without a memory fence: the LDS DMA of the next stage
+// keeps flying across it (a __syncthreads fence would wait for it).  The
+// "memory" clobber keeps the compiler from moving LDS accesses across.
+__device__ __forceinline__ void barrier_no_fence() { asm volatile("s_barrier" ::: "memory"); }
 
 // The sliced product for one output block of (32 WM) x (32 WN).  Each K-stage
 // is the block's digit tiles (A and B, all S slices, 2 KiB per 64-row tile)
 // copied from memory straight into LDS with 16-byte global_load_lds (no
-// staging registers); stage k + 1 is in flight while the digit-pair MFMAs of
-// stage k run.
-template <class Dg, int WM, int WN, int NST, int WPS>
+// staging registers).  Three LDS slots form a ring: while the MFMAs of stage
+// k run, stages k + 1 (landed or landing) and k + 2 (issued at the start of
+// stage k) are in flight, so a DMA has two stages' time to arrive.
+template <class Dg, int WM, int WN, int WPS>
 __global__ __launch_bounds__(64 * WM * WN, WPS) void gemm_sliced(
     int64_t M, int64_t N, int nBI, int nBJ, int nBK, int bk0, int bk1,
     const uint8_t *__restrict__ Ap, const uint8_t *__restrict__ Bp,
@@ -462,13 +512,9 @@ __global__ __launch_bounds__(64 * WM * WN, WPS) void gemm_sliced(
     constexpr int kSlotBytes = kS * (kTA + kTB) * kTileBytes;
     constexpr int kHalves = 2 * kS * (kTA + kTB);         // 1 KiB wavefront loads per stage
     constexpr int kQ = kHalves / kWaves, kR = kHalves % kWaves;
-    uint8_t *slots[NST];
-    slots[0] = lds_slot<kSlotBytes, 0>();
-    slots[1] = lds_slot<kSlotBytes, 1>();
-    if constexpr (NST > 2)
-        slots[2] = lds_slot<kSlotBytes, 2>();
-    if constexpr (NST > 3)
-        slots[3] = lds_slot<kSlotBytes, 3>();
+    uint8_t *const slot0 = lds_slot<kSlotBytes, 0>();
+    uint8_t *const slot1 = lds_slot<kSlotBytes, 1>();
+    uint8_t *const slot2 = lds_slot<kSlotBytes, 2>();
 
     const int bj = blockIdx.x, bi = blockIdx.y;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -488,7 +534,8 @@ __global__ __launch_bounds__(64 * WM * WN, WPS) void gemm_sliced(
     }
 
     // Half-tile h of a stage: A halves first (slice-major, tile, half),
-    // then B halves.  Wavefront w loads halves w, w + kWaves, ...
+    // then B halves.  Wavefront w loads halves w, w + kWaves, ... (kQ or
+    // kQ + 1 instructions).
     auto fetch = [&](int bk, uint8_t *slot) {
 #pragma unroll
         for (int j = 0; j < kQ + (kR ? 1 : 0); ++j) {
@@ -513,6 +560,18 @@ __global__ __launch_bounds__(64 * WM * WN, WPS) void gemm_sliced(
         }
     };
 
+    // Wait until only the newest stage's DMA (issued last, when `newest`)
+    // may be outstanding: a wavefront issues kQ + 1 instructions per stage
+    // if wave < kR, else kQ, and vmcnt counts them in issue order.
+    auto wait_older_stages = [&](bool newest) {
+        if (!newest)
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+        else if (kR != 0 && wave < kR)
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm(kQ + 1));
+        else
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm(kQ));
+    };
+
     // Operand rows of this lane: A row wm*32 + lane%32 lives in A tile
     // (wm / 2) at row 32*(wm % 2) + lane%32; likewise B.
     const int ta = wm >> 1, rla = 32 * (wm & 1) + (lane & 31);
@@ -520,30 +579,43 @@ __global__ __launch_bounds__(64 * WM * WN, WPS) void gemm_sliced(
     const int oa = ta * kTileBytes + tile_swizzle(rla, lane >> 5);
     const int ob = kS * kTA * kTileBytes + tb * kTileBytes + tile_swizzle(rlb, lane >> 5);
 
-    // One K-stage: the fragments of stage bk are read from LDS into
-    // registers first, then the DMA of stage bk + 1 is issued into the other
-    // slot (free: every wavefront finished reading it before the last
-    // barrier), then the digit-pair MFMAs run from registers while the DMA
-    // flies; the stage ends by waiting for this wavefront's DMA share and a
-    // barrier.  (The compiler orders LDS reads after an LDS DMA with a full
-    // vmcnt wait; reading before issuing keeps that wait off the critical
-    // path.)
-    auto stage = [&](const uint8_t *slot, uint8_t *next_slot, int bk) {
+    // One K-stage, reading `slot` (stage bk, landed) and filling `dma_slot`
+    // with stage bk + 2 (its previous content, stage bk - 1, was read by
+    // every wavefront before the last barrier).  Fragments are read in the
+    // order the MFMAs use them (fb[0], fa[0..6], fb[1..6]), so that the
+    // first MFMA needs only the first two reads.  The stage ends once this wavefront's share of stage bk + 1 has
+    // landed (only stage bk + 2 may still be in flight) and every wavefront
+    // has arrived.
+    auto stage = [&](const uint8_t *slot, uint8_t *dma_slot, int bk) {
+        const bool more = bk + 2 < bk1;
         uint4 fa[kS], fb[kS];
+        fb[0] = *reinterpret_cast<const uint4 *>(slot + ob);
 #pragma unroll
-        for (int t = 0; t < kS; ++t) {
+        for (int t = 0; t < kS; ++t)
             fa[t] = *reinterpret_cast<const uint4 *>(slot + t * kTA * kTileBytes + oa);
-            fb[t] = *reinterpret_cast<const uint4 *>(slot + t * kTB * kTileBytes + ob);
-        }
-        if (bk + 1 < bk1)
-            fetch(bk + 1, next_slot);
-        // digit pairs (t, u), t + u <= S - 1; consecutive instructions feed
-        // different diagonal accumulators
 #pragma unroll
-        for (int u = 0; u < kS; ++u)
+        for (int u = 1; u < kS; ++u)
+            fb[u] = *reinterpret_cast<const uint4 *>(slot + u * kTB * kTileBytes + ob);
+        // the DMA goes out after the reads: a conservative wait the compiler
+        // may place before the reads then never covers this stage's DMA.
+        // (Scheduling fences only for int8: the BF16 kernel's ~450 live
+        // registers leave the scheduler no room for them.)
+        if constexpr (Dg::kExtractStages == 0)
+            __builtin_amdgcn_sched_barrier(0);
+        if (more)
+            fetch(bk + 2, dma_slot);
+        if constexpr (Dg::kExtractStages == 0)
+            __builtin_amdgcn_sched_barrier(0);
+        // digit pairs (t, u), t + u <= S - 1, row by row; consecutive
+        // instructions feed different diagonal accumulators
+#pragma unroll
+        for (int u = 0; u < kS; ++u) {
 #pragma unroll
             for (int t = 0; t + u < kS; ++t)
                 acc[t + u] = mma(fa[t], fb[u], acc[t + u], Dg{});
+            if constexpr (Dg::kExtractStages == 0)
+                __builtin_amdgcn_sched_barrier(0);
+        }
         if constexpr (Dg::kExtractStages > 0) {
             if ((bk - bk0 + 1) % Dg::kExtractStages == 0 || bk + 1 == bk1) {
 #pragma unroll
@@ -555,49 +627,209 @@ __global__ __launch_bounds__(64 * WM * WN, WPS) void gemm_sliced(
                     }
             }
         }
-        // keep the MFMAs above the barrier: its vmcnt wait must not be
-        // scheduled before the work it is meant to overlap
         __builtin_amdgcn_sched_barrier(0);
-        __syncthreads();   // waits for this wavefront's DMA, then the barrier
+        wait_older_stages(more);
+        barrier_no_fence();
     };
 
-    static_assert(NST == 2, "two-slot ring");
     if (bk0 < bk1)
-        fetch(bk0, slots[0]);
-    __syncthreads();
-    for (int bk = bk0; bk < bk1; bk += 2) {
-        stage(slots[0], slots[1], bk);
-        if (bk + 1 < bk1)
-            stage(slots[1], slots[0], bk + 1);
+        fetch(bk0, slot0);
+    if (bk0 + 1 < bk1)
+        fetch(bk0 + 1, slot1);
+    wait_older_stages(bk0 + 1 < bk1);
+    barrier_no_fence();
+    // (The two loop forms are equivalent; each is the one the register
+    // allocator handles without spilling for its digit type.)
+    if constexpr (Dg::kExtractStages == 0) {
+        for (int bk = bk0; bk < bk1; bk += 3) {
+            stage(slot0, slot2, bk);
+            if (bk + 1 < bk1)
+                stage(slot1, slot0, bk + 1);
+            if (bk + 2 < bk1)
+                stage(slot2, slot1, bk + 2);
+        }
+    } else {
+        for (int bk = bk0; bk < bk1; bk += 3) {
+            stage(slot0, slot2, bk);
+            if (bk + 1 >= bk1)
+                break;
+            stage(slot1, slot0, bk + 1);
+            if (bk + 2 >= bk1)
+                break;
+            stage(slot2, slot1, bk + 2);
+        }
     }
 
-    // Epilogue: lane holds C[8*(r/4) + 4*(lane/32) + (r%4)][lane%32] of the
-    // wavefront's 32x32 block for r = 0..15.
-    const int64_t j = static_cast<int64_t>(bj) * (32 * WN) + wn * 32 + (lane & 31);
-    const int fj = j < N ? exponent_bound(colmax[j]) : 0;
+    store_block<Dg, WM, WN>(acc, iacc, M, N, bi, bj, wm, wn, lane, rowmax, colmax, Ch, Cl, ldc,
+                            accumulate);
+}
+
+// s_waitcnt immediate that waits until at most n LDS operations of this
+// wavefront are outstanding.
+constexpr int lgkmcnt_imm(int n) { return 15 | (3 << 14) | (7 << 4) | ((n & 15) << 8); }
+
+// The int8 product with a ping-pong schedule.  The 8 wavefronts form two
+// groups (waves 0-3 and 4-7: one of each on every SIMD) that run half a
+// K-stage apart: while one group reads a stage's fragments from LDS, the
+// other runs the MFMAs of the fragments it read before, so the LDS reads
+// land under the matrix-core work of the other group.  Two barriers per
+// stage k:
+//   phase 1: group 0 reads stage k, then issues its share of the DMA of
+//            stage k + 2;  group 1 multiplies stage k - 1
+//   phase 2: group 0 multiplies stage k;  group 1 reads stage k, then
+//            issues its share of the DMA of stage k + 2
+// Three LDS slots: the DMA of stage k + 2 fills the slot of stage k - 1,
+// which both groups finished reading before the last barrier (group 1
+// waits for its reads to land before that barrier).  A wavefront waits for
+// its previous DMA share at the start of its next read phase, one stage
+// after issuing it, and so before the barrier that precedes any read of it.
+template <int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN, 2) void gemm_sliced_pp(
+    int64_t M, int64_t N, int nBI, int nBJ, int nBK, int bk0, int bk1,
+    const uint8_t *__restrict__ Ap, const uint8_t *__restrict__ Bp,
+    const uint32_t *__restrict__ rowmax, const uint32_t *__restrict__ colmax,
+    float *__restrict__ Ch, float *__restrict__ Cl, int64_t ldc, int accumulate)
+{
+    using Dg = DigitsI8;
+    constexpr int kWaves = WM * WN;
+    static_assert(kWaves == 8, "two groups of four wavefronts");
+    constexpr int kTA = WM / 2, kTB = WN / 2;
+    constexpr int kSlotBytes = kS * (kTA + kTB) * kTileBytes;
+    constexpr int kHalves = 2 * kS * (kTA + kTB);
+    constexpr int kQ = kHalves / kWaves, kR = kHalves % kWaves;
+    uint8_t *const slot0 = lds_slot<kSlotBytes, 0>();
+    uint8_t *const slot1 = lds_slot<kSlotBytes, 1>();
+    uint8_t *const slot2 = lds_slot<kSlotBytes, 2>();
+
+    const int bj = blockIdx.x, bi = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // wavefront index as a scalar, so that the group test is a uniform branch
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / WN, wn = wave % WN;
+    const int64_t a_slice = static_cast<int64_t>(nBI) * nBK * kTileBytes;
+    const int64_t b_slice = static_cast<int64_t>(nBJ) * nBK * kTileBytes;
+
+    i32x16 acc[kS];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int64_t i = static_cast<int64_t>(bi) * (32 * WM) + wm * 32 + m;
-        if (i >= M || j >= N)
-            continue;
-        __int128 T = 0;
+    for (int d = 0; d < kS; ++d)
 #pragma unroll
-        for (int d = 0; d < kS; ++d) {
-            int s;
-            if constexpr (Dg::kExtractStages > 0)
-                s = iacc[d][r];
-            else
-                s = acc[d][r];
-            T = (T << 8) + static_cast<__int128>(s);
+        for (int r = 0; r < 16; ++r)
+            acc[d][r] = 0;
+
+    auto fetch = [&](int bk, uint8_t *slot) {
+#pragma unroll
+        for (int j = 0; j < kQ + (kR ? 1 : 0); ++j) {
+            const int h = wave + j * kWaves;
+            if (h < kHalves) {
+                const int tile = h >> 1, half = h & 1;
+                const uint8_t *src;
+                if (tile < kS * kTA) {
+                    const int t = tile / kTA, tt = tile % kTA;
+                    src = Ap + t * a_slice + tile_base(0, bi * kTA + tt, bk, nBI, nBK);
+                } else {
+                    const int tb = tile - kS * kTA;
+                    const int t = tb / kTB, tt = tb % kTB;
+                    src = Bp + t * b_slice + tile_base(0, bj * kTB + tt, bk, nBJ, nBK);
+                }
+                src += half * 1024 + lane * 16;
+                uint8_t *dst = slot + tile * kTileBytes + half * 1024;
+                __builtin_amdgcn_global_load_lds((global_void_ptr)(const void *)src,
+                                                 (lds_void_ptr)(void *)dst, 16, 0, 0);
+            }
         }
-        float h, l;
-        i128_to_ff(T, exponent_bound(rowmax[i]) + fj + kEpiShift, h, l);
-        if (accumulate)
-            ffd::add22(Ch[i * ldc + j], Cl[i * ldc + j], h, l, h, l);
-        Ch[i * ldc + j] = h;
-        Cl[i * ldc + j] = l;
+    };
+
+    const int ta = wm >> 1, rla = 32 * (wm & 1) + (lane & 31);
+    const int tb = wn >> 1, rlb = 32 * (wn & 1) + (lane & 31);
+    const int oa = ta * kTileBytes + tile_swizzle(rla, lane >> 5);
+    const int ob = kS * kTA * kTileBytes + tb * kTileBytes + tile_swizzle(rlb, lane >> 5);
+
+    uint4 fa[kS], fb[kS];
+    auto read_frags = [&](const uint8_t *slot) {
+        fb[0] = *reinterpret_cast<const uint4 *>(slot + ob);
+#pragma unroll
+        for (int t = 0; t < kS; ++t)
+            fa[t] = *reinterpret_cast<const uint4 *>(slot + t * kTA * kTileBytes + oa);
+#pragma unroll
+        for (int u = 1; u < kS; ++u)
+            fb[u] = *reinterpret_cast<const uint4 *>(slot + u * kTB * kTileBytes + ob);
+    };
+    auto mfmas = [&]() {
+#pragma unroll
+        for (int u = 0; u < kS; ++u) {
+#pragma unroll
+            for (int t = 0; t + u < kS; ++t)
+                acc[t + u] = mma(fa[t], fb[u], acc[t + u], Dg{});
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    // A read phase: this wavefront's previous DMA share (stage bk + 1) has
+    // landed, the fragments of stage bk are read, and the share of stage
+    // bk + 2 goes out.
+    auto read_phase = [&](const uint8_t *slot, uint8_t *dma_slot, int bk) {
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+        read_frags(slot);
+        __builtin_amdgcn_sched_barrier(0);
+        if (bk + 2 < bk1)
+            fetch(bk + 2, dma_slot);
+        __builtin_amdgcn_sched_barrier(0);
+    };
+
+    // stages bk0 and bk0 + 1 in flight; stage bk0 landed everywhere
+    if (bk0 < bk1)
+        fetch(bk0, slot0);
+    if (bk0 + 1 < bk1)
+        fetch(bk0 + 1, slot1);
+    if (bk0 + 1 < bk1) {
+        if (kR != 0 && wave < kR)
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm(kQ + 1));
+        else
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm(kQ));
+    } else {
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
     }
+    barrier_no_fence();
+
+    if (wave < 4) {
+        auto stage0 = [&](const uint8_t *slot, uint8_t *dma_slot, int bk) {
+            read_phase(slot, dma_slot, bk);
+            barrier_no_fence();
+            mfmas();
+            __builtin_amdgcn_sched_barrier(0);
+            barrier_no_fence();
+        };
+        for (int bk = bk0; bk < bk1; bk += 3) {
+            stage0(slot0, slot2, bk);
+            if (bk + 1 < bk1)
+                stage0(slot1, slot0, bk + 1);
+            if (bk + 2 < bk1)
+                stage0(slot2, slot1, bk + 2);
+        }
+    } else {
+        auto stage1 = [&](const uint8_t *slot, uint8_t *dma_slot, int bk) {
+            if (bk > bk0)
+                mfmas();
+            __builtin_amdgcn_sched_barrier(0);
+            barrier_no_fence();
+            read_phase(slot, dma_slot, bk);
+            // reads landed before the barrier: the DMA of the next stage
+            // overwrites the slot of the stage before this one
+            __builtin_amdgcn_s_waitcnt(lgkmcnt_imm(0));
+            barrier_no_fence();
+        };
+        for (int bk = bk0; bk < bk1; bk += 3) {
+            stage1(slot0, slot2, bk);
+            if (bk + 1 < bk1)
+                stage1(slot1, slot0, bk + 1);
+            if (bk + 2 < bk1)
+                stage1(slot2, slot1, bk + 2);
+        }
+        if (bk0 < bk1)
+            mfmas();   // the last stage
+    }
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    store_block<Dg, WM, WN>(acc, acc, M, N, bi, bj, wm, wn, lane, rowmax, colmax, Ch, Cl, ldc,
+                            accumulate);
 }
 
 struct SliceGeom {
@@ -671,9 +903,14 @@ ff_status sliced_gemm(int64_t M, int64_t N, int64_t K, const float *Ah, const fl
     int bk0 = 0;
     do {
         const int bk1 = (bk0 + stages_per_chunk < g.nBK) ? bk0 + stages_per_chunk : g.nBK;
-        hipLaunchKernelGGL((gemm_sliced<Dg, Sh::WM, Sh::WN, Sh::NST, Sh::WAVES_PER_SIMD>), grid,
-                           dim3(64 * Sh::WM * Sh::WN), 0, st, M, N, g.nBI, g.nBJ, g.nBK, bk0, bk1,
-                           Ap, Bp, rowmax, colmax, Ch, Cl, ldc, bk0 > 0 ? 1 : 0);
+        if constexpr (Dg::kExtractStages == 0)
+            hipLaunchKernelGGL((gemm_sliced_pp<Sh::WM, Sh::WN>), grid, dim3(64 * Sh::WM * Sh::WN),
+                               0, st, M, N, g.nBI, g.nBJ, g.nBK, bk0, bk1, Ap, Bp, rowmax, colmax,
+                               Ch, Cl, ldc, bk0 > 0 ? 1 : 0);
+        else
+            hipLaunchKernelGGL((gemm_sliced<Dg, Sh::WM, Sh::WN, Sh::WAVES_PER_SIMD>), grid,
+                               dim3(64 * Sh::WM * Sh::WN), 0, st, M, N, g.nBI, g.nBJ, g.nBK, bk0,
+                               bk1, Ap, Bp, rowmax, colmax, Ch, Cl, ldc, bk0 > 0 ? 1 : 0);
         bk0 = bk1;
     } while (bk0 < g.nBK);
     return ffh::launch_status();
