@@ -234,7 +234,9 @@ __global__ __launch_bounds__(256) void fill_u32(uint32_t *p, int64_t n)
 }
 
 // rowmax[i] = max_k |A_hi[i, k]| (as bits).  One wavefront per (row, 4096-k
-// segment); integer atomicMax, so the result does not depend on order.
+// segment), 16-byte loads when the rows are 16-byte aligned; integer
+// atomicMax, so the result does not depend on order.
+template <bool VEC>
 __global__ __launch_bounds__(256) void absmax_rows(int64_t M, int64_t K,
                                                    const float *__restrict__ Ah, int64_t lda,
                                                    uint32_t *__restrict__ rowmax)
@@ -245,9 +247,21 @@ __global__ __launch_bounds__(256) void absmax_rows(int64_t M, int64_t K,
         return;
     const int64_t k0 = static_cast<int64_t>(blockIdx.x) * 4096;
     const int64_t k1 = (k0 + 4096 < K) ? k0 + 4096 : K;
+    const float *a = Ah + row * lda;
     uint32_t m = 0;
-    for (int64_t k = k0 + lane; k < k1; k += 64)
-        m = max(m, f32_bits(Ah[row * lda + k]) & 0x7fffffffu);
+    if (VEC) {
+        const int64_t kv = k0 + ((k1 - k0) & ~int64_t(255));   // whole 256-entry steps
+        for (int64_t k = k0 + 4 * lane; k < kv; k += 256) {
+            const float4 v = *reinterpret_cast<const float4 *>(a + k);
+            m = max(m, max(max(f32_bits(v.x) & 0x7fffffffu, f32_bits(v.y) & 0x7fffffffu),
+                           max(f32_bits(v.z) & 0x7fffffffu, f32_bits(v.w) & 0x7fffffffu)));
+        }
+        for (int64_t k = kv + lane; k < k1; k += 64)
+            m = max(m, f32_bits(a[k]) & 0x7fffffffu);
+    } else {
+        for (int64_t k = k0 + lane; k < k1; k += 64)
+            m = max(m, f32_bits(a[k]) & 0x7fffffffu);
+    }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1)
         m = max(m, static_cast<uint32_t>(__shfl_xor(static_cast<int>(m), off, 64)));
@@ -255,7 +269,8 @@ __global__ __launch_bounds__(256) void absmax_rows(int64_t M, int64_t K,
         atomicMax(&rowmax[row], m);
 }
 
-// colmax[j] = max_k |B_hi[k, j]|: thread per column, 256-row bands.
+// colmax[j] = max_k |B_hi[k, j]|: thread per column, 64-row bands, eight
+// independent loads in flight per thread.
 __global__ __launch_bounds__(256) void absmax_cols(int64_t K, int64_t N,
                                                    const float *__restrict__ Bh, int64_t ldb,
                                                    uint32_t *__restrict__ colmax)
@@ -263,13 +278,23 @@ __global__ __launch_bounds__(256) void absmax_cols(int64_t K, int64_t N,
     const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     if (j >= N)
         return;
-    const int64_t k0 = static_cast<int64_t>(blockIdx.y) * 256;
-    const int64_t k1 = (k0 + 256 < K) ? k0 + 256 : K;
-    uint32_t m = 0;
-    for (int64_t k = k0; k < k1; ++k)
-        m = max(m, f32_bits(Bh[k * ldb + j]) & 0x7fffffffu);
-    if (m)
-        atomicMax(&colmax[j], m);
+    const int64_t k0 = static_cast<int64_t>(blockIdx.y) * 64;
+    const int64_t k1 = (k0 + 64 < K) ? k0 + 64 : K;
+    uint32_t m[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t k = k0;
+    for (; k + 8 <= k1; k += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            m[u] = max(m[u], f32_bits(Bh[(k + u) * ldb + j]) & 0x7fffffffu);
+    }
+    for (; k < k1; ++k)
+        m[0] = max(m[0], f32_bits(Bh[k * ldb + j]) & 0x7fffffffu);
+    uint32_t r = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        r = max(r, m[u]);
+    if (r)
+        atomicMax(&colmax[j], r);
 }
 
 // One 16-byte chunk of every slice for the entries (r, k0 .. k0 + per - 1)
@@ -313,29 +338,57 @@ __device__ __forceinline__ void slice_chunk(Load load, bool row_ok, int64_t k0, 
 
 // A digit planes: workgroup = (64-row tile, K stage), 128 threads, thread =
 // (row, chunk).
+// Digit planes of A.  A workgroup covers 32 rows by 8 consecutive 16-byte
+// chunks (4 K-stages) of each row; a thread converts one chunk: kPer
+// consecutive entries of its row, read with 16-byte loads when the rows are
+// 16-byte aligned (adjacent threads read adjacent 64- or 32-byte pieces of
+// the row).  Rows at or beyond M and entries at or beyond K give zero
+// digits (the tiles are padded).
 template <class Dg>
-__global__ __launch_bounds__(128) void slice_rows(int64_t M, int64_t K,
+__global__ __launch_bounds__(256) void slice_rows(int64_t M, int64_t K,
                                                   const float *__restrict__ Ah,
                                                   const float *__restrict__ Al, int64_t lda,
                                                   const uint32_t *__restrict__ rowmax, int nBI,
-                                                  int nBK, uint8_t *__restrict__ planes)
+                                                  int nBK, uint8_t *__restrict__ planes, int vec)
 {
-    const int bk = blockIdx.x, bi = blockIdx.y;
-    const int row = threadIdx.x >> 1, chunk = threadIdx.x & 1;
-    const int64_t i = static_cast<int64_t>(bi) * kTile + row;
+    constexpr int kPer = 16 / Dg::kEsize;                 // entries per chunk
+    constexpr int kChunks = Dg::kStageK / kPer;           // chunks per K-stage (2)
+    const int c = threadIdx.x & 7;
+    const int64_t i = static_cast<int64_t>(blockIdx.y) * 32 + (threadIdx.x >> 3);
+    const int64_t kc = static_cast<int64_t>(blockIdx.x) * 8 + c;
+    const int bk = static_cast<int>(kc / kChunks), chunk = static_cast<int>(kc % kChunks);
+    if (bk >= nBK || i >= static_cast<int64_t>(nBI) * kTile)
+        return;
     const bool ok = i < M;
     const int e = ok ? exponent_bound(rowmax[i]) : 0;
-    const int64_t k0 = static_cast<int64_t>(bk) * Dg::kStageK + chunk * (16 / Dg::kEsize);
-    auto load = [&](int64_t k, float &hi, float &lo) {
-        hi = Ah[i * lda + k];
-        lo = Al[i * lda + k];
-    };
-    slice_chunk<Dg>(load, ok, k0, K, e, planes, tile_base(0, bi, bk, nBI, nBK),
-                    static_cast<int64_t>(nBI) * nBK * kTileBytes, tile_swizzle(row, chunk));
+    const int64_t k0 = kc * kPer;
+    const int bi = static_cast<int>(i / kTile), row = static_cast<int>(i % kTile);
+    const int64_t slice_stride = static_cast<int64_t>(nBI) * nBK * kTileBytes;
+    const int in_tile = tile_swizzle(row, chunk);
+    if (vec && ok && k0 + kPer <= K) {
+        float hv[kPer], lv[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; q += 4) {
+            const float4 h4 = *reinterpret_cast<const float4 *>(Ah + i * lda + k0 + q);
+            const float4 l4 = *reinterpret_cast<const float4 *>(Al + i * lda + k0 + q);
+            hv[q] = h4.x; hv[q + 1] = h4.y; hv[q + 2] = h4.z; hv[q + 3] = h4.w;
+            lv[q] = l4.x; lv[q + 1] = l4.y; lv[q + 2] = l4.z; lv[q + 3] = l4.w;
+        }
+        auto load = [&](int64_t k, float &hi, float &lo) {
+            hi = hv[k - k0];
+            lo = lv[k - k0];
+        };
+        slice_chunk<Dg>(load, true, k0, K, e, planes, tile_base(0, bi, bk, nBI, nBK),
+                        slice_stride, in_tile);
+    } else {
+        auto load = [&](int64_t k, float &hi, float &lo) {
+            hi = Ah[i * lda + k];
+            lo = Al[i * lda + k];
+        };
+        slice_chunk<Dg>(load, ok, k0, K, e, planes, tile_base(0, bi, bk, nBI, nBK),
+                        slice_stride, in_tile);
+    }
 }
-
-// B^T digit planes: workgroup = (64-column tile, K stage), 128 threads;
-// lanes take consecutive columns (coalesced reads of B's rows).
 template <class Dg>
 __global__ __launch_bounds__(128) void slice_cols(int64_t K, int64_t N,
                                                   const float *__restrict__ Bh,
@@ -870,7 +923,7 @@ ff_status sliced_gemm(int64_t M, int64_t N, int64_t K, const float *Ah, const fl
         return FF_ERR_WORKSPACE;
     if (!ffh::aligned(ws, 256))
         return FF_ERR_ALIGN;
-    if (g.nBI > 65535 || g.nBJ > 65535 || ffh::cdiv(M, 4) > 65535 || ffh::cdiv(K, 256) > 65535)
+    if (g.nBI > 32767 || g.nBJ > 65535 || ffh::cdiv(M, 4) > 65535 || ffh::cdiv(K, 64) > 65535)
         return FF_ERR_SIZE;
     char *base = static_cast<char *>(ws);
     uint32_t *rowmax = reinterpret_cast<uint32_t *>(base + g.off_rowmax);
@@ -883,16 +936,23 @@ ff_status sliced_gemm(int64_t M, int64_t N, int64_t K, const float *Ah, const fl
     hipLaunchKernelGGL(fill_u32, dim3(static_cast<unsigned>(fill_blocks < 4096 ? fill_blocks : 4096)),
                        dim3(256), 0, st, rowmax, nfill);
     if (K > 0) {
-        hipLaunchKernelGGL(absmax_rows,
-                           dim3(static_cast<unsigned>(ffh::cdiv(K, 4096)),
-                                static_cast<unsigned>(ffh::cdiv(M, 4))),
-                           dim3(256), 0, st, M, K, Ah, lda, rowmax);
+        const bool rows_vec = lda % 4 == 0 && ffh::aligned(Ah, 16) && ffh::aligned(Al, 16);
+        const dim3 rgrid(static_cast<unsigned>(ffh::cdiv(K, 4096)),
+                         static_cast<unsigned>(ffh::cdiv(M, 4)));
+        if (rows_vec)
+            hipLaunchKernelGGL(absmax_rows<true>, rgrid, dim3(256), 0, st, M, K, Ah, lda, rowmax);
+        else
+            hipLaunchKernelGGL(absmax_rows<false>, rgrid, dim3(256), 0, st, M, K, Ah, lda, rowmax);
         hipLaunchKernelGGL(absmax_cols,
                            dim3(static_cast<unsigned>(ffh::cdiv(N, 256)),
-                                static_cast<unsigned>(ffh::cdiv(K, 256))),
+                                static_cast<unsigned>(ffh::cdiv(K, 64))),
                            dim3(256), 0, st, K, N, Bh, ldb, colmax);
-        hipLaunchKernelGGL((slice_rows<Dg>), dim3(g.nBK, g.nBI), dim3(128), 0, st, M, K, Ah, Al,
-                           lda, rowmax, g.nBI, g.nBK, Ap);
+        constexpr int kChunks = Dg::kStageK / (16 / Dg::kEsize);
+        hipLaunchKernelGGL((slice_rows<Dg>),
+                           dim3(static_cast<unsigned>(ffh::cdiv(static_cast<int64_t>(g.nBK) * kChunks, 8)),
+                                static_cast<unsigned>(g.nBI * (kTile / 32))),
+                           dim3(256), 0, st, M, K, Ah, Al, lda, rowmax, g.nBI, g.nBK, Ap,
+                           rows_vec ? 1 : 0);
         hipLaunchKernelGGL((slice_cols<Dg>), dim3(g.nBK, g.nBJ), dim3(128), 0, st, K, N, Bh, Bl,
                            ldb, colmax, g.nBJ, g.nBK, Bp);
     }
