@@ -183,21 +183,52 @@ __global__ __launch_bounds__(BLOCK) void matvec_bwd_band(
 }
 
 // dx_j = partial sums of column j added in band order.
-__global__ __launch_bounds__(256) void matvec_bwd_combine(int64_t N, int64_t nbands,
-                                                          const float2 *__restrict__ part,
-                                                          float *__restrict__ dxh,
-                                                          float *__restrict__ dxl)
+// dx_j = sum over bands of the per-band partials, for 64 columns per
+// workgroup: eight groups of threads take bands g, g + 8, ... (coalesced
+// 512-byte rows of partials, several loads in flight per thread), then the
+// eight group sums are added in a fixed tree through LDS.
+constexpr int kCombineGroups = 8;
+
+__global__ __launch_bounds__(64 * kCombineGroups) void matvec_bwd_combine(
+    int64_t N, int64_t nbands, const float2 *__restrict__ part, float *__restrict__ dxh,
+    float *__restrict__ dxl)
 {
-    const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (j >= N)
-        return;
+    __shared__ float2 sums[kCombineGroups][64];
+    const int col = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * 64 + col;
     float h = 0.0f, l = 0.0f;
-    for (int64_t b = 0; b < nbands; ++b) {
-        const float2 p = part[b * N + j];
-        ffd::add22(h, l, p.x, p.y, h, l);
+    if (j < N) {
+        int64_t b = grp;
+        for (; b + 3 * kCombineGroups < nbands; b += 4 * kCombineGroups) {
+            float2 p[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                p[u] = part[(b + u * kCombineGroups) * N + j];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                ffd::add22(h, l, p[u].x, p[u].y, h, l);
+        }
+        for (; b < nbands; b += kCombineGroups) {
+            const float2 p = part[b * N + j];
+            ffd::add22(h, l, p.x, p.y, h, l);
+        }
     }
-    dxh[j] = h;
-    dxl[j] = l;
+    sums[grp][col] = make_float2(h, l);
+    __syncthreads();
+#pragma unroll
+    for (int w = kCombineGroups / 2; w >= 1; w >>= 1) {
+        if (grp < w) {
+            const float2 a = sums[grp][col], c = sums[grp + w][col];
+            float rh, rl;
+            ffd::add22(a.x, a.y, c.x, c.y, rh, rl);
+            sums[grp][col] = make_float2(rh, rl);
+        }
+        __syncthreads();
+    }
+    if (grp == 0 && j < N) {
+        dxh[j] = sums[0][col].x;
+        dxl[j] = sums[0][col].y;
+    }
 }
 
 // Plain backward, dx: one thread per column, rows in order.
@@ -396,8 +427,8 @@ ff_status ff_matvec_backward(int64_t M, int64_t N, const float *A_hi, const floa
 #undef FF_BWD_LAUNCH
     }
     if (want_dx)
-        hipLaunchKernelGGL(matvec_bwd_combine, dim3(static_cast<unsigned>(ffh::cdiv(N, 256))),
-                           dim3(256), 0, st, N, nbands, part, dx_hi, dx_lo);
+        hipLaunchKernelGGL(matvec_bwd_combine, dim3(static_cast<unsigned>(ffh::cdiv(N, 64))),
+                           dim3(64 * kCombineGroups), 0, st, N, nbands, part, dx_hi, dx_lo);
     return ffh::launch_status();
 }
 

@@ -72,39 +72,70 @@ __device__ __forceinline__ int64_t clamp_offset(int64_t o, int64_t total)
 }
 
 // Planning launch (one workgroup): chunk counts of the vectors and their
-// exclusive scan.
+// exclusive scan.  Each round covers kPlanItems consecutive vectors per
+// thread: a serial scan in the thread, a shuffle scan across the wavefront,
+// and a scan of the wavefront totals by the first wavefront.
+constexpr int kPlanItems = 4;
+
+__device__ __forceinline__ int64_t wave_inclusive_scan(int64_t v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t o = __shfl_up(v, d, 64);
+        if (lane >= d)
+            v += o;
+    }
+    return v;
+}
+
 __global__ __launch_bounds__(kPlanBlock) void dot_plan(const int64_t *__restrict__ offsets,
                                                        int32_t nvec, int64_t total, int64_t chunk,
                                                        Workspace w)
 {
-    __shared__ int64_t scan[kPlanBlock];
+    constexpr int kWaves = kPlanBlock / 64;
+    __shared__ int64_t wave_sum[kWaves];
     __shared__ int64_t carry;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0)
         carry = 0;
     __syncthreads();
-    for (int64_t base = 0; base < nvec; base += kPlanBlock) {
-        const int64_t v = base + tid;
-        int64_t n = 0;
-        if (v < nvec) {
-            const int64_t b = clamp_offset(offsets[v], total);
-            const int64_t e = clamp_offset(offsets[v + 1], total);
-            const int64_t len = e > b ? e - b : 0;
-            n = (len + chunk - 1) / chunk;
+    for (int64_t base = 0; base < nvec; base += kPlanBlock * kPlanItems) {
+        int64_t n[kPlanItems];
+        int64_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < kPlanItems; ++k) {
+            const int64_t v = base + static_cast<int64_t>(tid) * kPlanItems + k;
+            n[k] = 0;
+            if (v < nvec) {
+                const int64_t b = clamp_offset(offsets[v], total);
+                const int64_t e = clamp_offset(offsets[v + 1], total);
+                const int64_t len = e > b ? e - b : 0;
+                n[k] = (len + chunk - 1) / chunk;
+            }
+            mine += n[k];
         }
-        scan[tid] = n;
+        const int64_t incl = wave_inclusive_scan(mine, lane);
+        if (lane == 63)
+            wave_sum[wave] = incl;
         __syncthreads();
-        for (int d = 1; d < kPlanBlock; d <<= 1) {   // Hillis-Steele inclusive scan
-            const int64_t add = tid >= d ? scan[tid - d] : 0;
-            __syncthreads();
-            scan[tid] += add;
-            __syncthreads();
+        if (wave == 0) {
+            const int64_t ws = lane < kWaves ? wave_sum[lane] : 0;
+            const int64_t wincl = wave_inclusive_scan(ws, lane);
+            if (lane < kWaves)
+                wave_sum[lane] = wincl - ws;   // exclusive
         }
-        if (v < nvec)
-            w.chunk_start[v] = carry + scan[tid] - n;
+        __syncthreads();
+        int64_t run = carry + wave_sum[wave] + incl - mine;
+#pragma unroll
+        for (int k = 0; k < kPlanItems; ++k) {
+            const int64_t v = base + static_cast<int64_t>(tid) * kPlanItems + k;
+            if (v < nvec)
+                w.chunk_start[v] = run;
+            run += n[k];
+        }
         __syncthreads();
         if (tid == kPlanBlock - 1)
-            carry += scan[tid];
+            carry = run;   // the last thread's running total ends the round
         __syncthreads();
     }
     if (tid == 0)
