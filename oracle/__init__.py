@@ -35,7 +35,8 @@ CFLAGS = [
     "-msse2", "-mfpmath=sse",
 ]
 
-ELEMENTWISE_OPS = {"add": 0, "sub": 1, "mul": 2, "mul_dekker": 3, "div": 4}
+ELEMENTWISE_OPS = {"add": 0, "sub": 1, "mul": 2, "mul_dekker": 3, "div": 4,
+                   "add_accurate": 5, "sub_accurate": 6}
 
 
 def build(force: bool = True, cc: str = "gcc", src: str = _SRC, out: str = _SO) -> str:
@@ -66,6 +67,8 @@ _SIGS = {
     "oracle_sub22": ([_F, _F, _F, _F, _F, _F, _i64], None),
     "oracle_mul22": ([_F, _F, _F, _F, _F, _F, _i64, _int], None),
     "oracle_div22": ([_F, _F, _F, _F, _F, _F, _i64, _int], None),
+    "oracle_add22_accurate": ([_F, _F, _F, _F, _F, _F, _i64], None),
+    "oracle_sub22_accurate": ([_F, _F, _F, _F, _F, _F, _i64], None),
     "oracle_elementwise": ([_int, _F, _F, _F, _F, _F, _F, _i64], _int),
     "oracle_dot_seq": ([_F, _F, _i64, _F], None),
     "oracle_dot_ff_seq": ([_F, _F, _i64, _F, _F, _i64, _i64, _F], None),
@@ -192,6 +195,17 @@ def add22(ah, al, bh, bl):
 def sub22(ah, al, bh, bl):
     """Add22 of a and -b."""
     return _binary("oracle_sub22", ah, al, bh, bl)
+
+
+def add22_accurate(ah, al, bh, bl):
+    """Cancellation-safe float-float sum (AccurateDWPlusDW of Joldes, Muller
+    and Popescu 2017): relative error below 3u^2/(1 - 4u), u = 2^-24."""
+    return _binary("oracle_add22_accurate", ah, al, bh, bl)
+
+
+def sub22_accurate(ah, al, bh, bl):
+    """The cancellation-safe sum of a and -b."""
+    return _binary("oracle_sub22_accurate", ah, al, bh, bl)
 
 
 def mul22(ah, al, bh, bl, dekker: bool = False):

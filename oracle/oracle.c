@@ -64,8 +64,9 @@ static void add12(float a, float b, float *s_out, float *r_out)
 }
 
 /* The "one test" Add12 the paper mentions next to the branch-free one
- * (section 4): Fast2Sum, exact when |a| >= |b|. Kept as a reference variant;
- * no operator below uses it. */
+ * (section 4): Fast2Sum, exact when |a| >= |b|.  None of the paper's
+ * operators uses it; the cancellation-safe addition below does, where its
+ * operands are ordered. */
 static void fast_add12(float a, float b, float *s_out, float *r_out)
 {
     float s = a + b;
@@ -141,6 +142,25 @@ static void add22(float ah, float al, float bh, float bl, float *rh, float *rl)
 static void sub22(float ah, float al, float bh, float bl, float *rh, float *rl)
 {
     add22(ah, al, -bh, -bl, rh, rl);
+}
+
+/* Cancellation-safe float-float addition (not in the paper, whose Add22
+ * bound is not relative under cancellation, Add22 theorem): the
+ * "AccurateDWPlusDW" algorithm of Joldes, Muller and Popescu (ACM TOMS 2017,
+ * Algorithm 6), relative error below 3u^2 / (1 - 4u), u = 2^-24:
+ *   (sh, sl) = TwoSum(ah, bh);  (th, tl) = TwoSum(al, bl);
+ *   c = sl + th;  (vh, vl) = Fast2Sum(sh, c);  w = tl + vl;
+ *   (rh, rl) = Fast2Sum(vh, w). */
+static void add22_accurate(float ah, float al, float bh, float bl, float *rh,
+                           float *rl)
+{
+    float sh, sl, th, tl, vh, vl;
+    add12(ah, bh, &sh, &sl);
+    add12(al, bl, &th, &tl);
+    float c = sl + th;
+    fast_add12(sh, c, &vh, &vl);
+    float w = tl + vl;
+    fast_add12(vh, w, rh, rl);
 }
 
 /* Mul22 theorem, with the final renormalisation of (t1, t3). */
@@ -226,9 +246,24 @@ void oracle_div22(const float *ah, const float *al, const float *bh,
         div22(ah[i], al[i], bh[i], bl[i], use_dekker, &rh[i], &rl[i]);
 }
 
+void oracle_add22_accurate(const float *ah, const float *al, const float *bh,
+                           const float *bl, float *rh, float *rl, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        add22_accurate(ah[i], al[i], bh[i], bl[i], &rh[i], &rl[i]);
+}
+
+void oracle_sub22_accurate(const float *ah, const float *al, const float *bh,
+                           const float *bl, float *rh, float *rl, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        add22_accurate(ah[i], al[i], -bh[i], -bl[i], &rh[i], &rl[i]);
+}
+
 /* Elementwise op selected by code: 0 add, 1 sub, 2 mul (FMA TwoProd),
- * 3 mul (Dekker TwoProd), 4 div (FMA TwoProd).  Used by the benchmark's CPU
- * leg so that one call times one operator over a sample. */
+ * 3 mul (Dekker TwoProd), 4 div (FMA TwoProd), 5 cancellation-safe add,
+ * 6 cancellation-safe sub.  Used by the benchmark's CPU leg so that one call
+ * times one operator over a sample. */
 int oracle_elementwise(int op, const float *ah, const float *al,
                        const float *bh, const float *bl, float *rh, float *rl,
                        int64_t n)
@@ -239,6 +274,8 @@ int oracle_elementwise(int op, const float *ah, const float *al,
     case 2: oracle_mul22(ah, al, bh, bl, rh, rl, n, 0); return 0;
     case 3: oracle_mul22(ah, al, bh, bl, rh, rl, n, 1); return 0;
     case 4: oracle_div22(ah, al, bh, bl, rh, rl, n, 0); return 0;
+    case 5: oracle_add22_accurate(ah, al, bh, bl, rh, rl, n); return 0;
+    case 6: oracle_sub22_accurate(ah, al, bh, bl, rh, rl, n); return 0;
     default: return -1;
     }
 }

@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 import test_oracle_operators as OPS
+import test_oracle_accurate_add as ACC
 import test_oracle_paper_tables as TAB
 import test_oracle_primitives as PRIM
 import test_oracle_reductions as RED
@@ -51,6 +52,13 @@ TAB_PINS = [
     lambda: TAB.test_ff_errors_against_fractions("mul22"),
     TAB.test_ff_errors_edge_cases,
 ]
+ACC_PINS = [
+    ACC.test_zero_low_words_is_the_exact_add12_pair,
+    ACC.test_identities,
+    lambda: ACC.test_relative_error_bound_holds_under_cancellation("cancel"),
+    lambda: ACC.test_relative_error_bound_holds_under_cancellation("random"),
+    lambda: ACC.test_relative_error_bound_holds_under_cancellation("gap"),
+]
 
 # (name, original text, planted text, pins expected to catch it)
 MUTATIONS = [
@@ -78,6 +86,10 @@ MUTATIONS = [
     ("exact_exponent", "*e = ex - 24;", "*e = ex - 23;", RED_PINS),
     ("dot_dropped_error_term", "        add22(acc_h, acc_l, p, e, &acc_h, &acc_l);",
      "        add22(acc_h, acc_l, p, 0.0f, &acc_h, &acc_l);", RED_PINS),
+    ("accurate_dropped_tl", "    float w = tl + vl;", "    float w = vl;", ACC_PINS),
+    ("accurate_sign", "    float c = sl + th;", "    float c = sl - th;", ACC_PINS),
+    ("accurate_low_pair", "    add12(al, bl, &th, &tl);", "    add12(al, bh, &th, &tl);", ACC_PINS),
+    ("accurate_final_order", "    fast_add12(vh, w, rh, rl);", "    fast_add12(w, vh, rh, rl);", ACC_PINS),
     ("mad_unfused", "r[i] = fmaf(a[i], b[i], c[i]);", "r[i] = a[i] * b[i] + c[i];",
      TAB_PINS),
     ("errors_dropped_low_word", "            la_add_f32(&exact, bl[i], 1);\n            la_add_f32(&lo, al[i], 1);",
