@@ -23,9 +23,9 @@ import json
 import sys
 
 OPS = ["Add", "Mul", "Mad", "Add12", "Mul12 (FMA)", "Mul12 (Dekker)", "Add22", "Mul22",
-       "Mul22 (Dekker)"]
+       "Mul22 (Dekker)", "Add22 (accurate)"]
 BYTES = {"Add": 12, "Mul": 12, "Mad": 16, "Add12": 16, "Mul12 (FMA)": 16, "Mul12 (Dekker)": 16,
-         "Add22": 24, "Mul22": 24, "Mul22 (Dekker)": 24}
+         "Add22": 24, "Mul22": 24, "Mul22 (Dekker)": 24, "Add22 (accurate)": 24}
 
 
 def main(argv=None) -> int:
@@ -65,6 +65,7 @@ def main(argv=None) -> int:
             "Add22": lambda st=stream: ff.ff_add(Av, Bv, out=Rv, stream=st),
             "Mul22": lambda st=stream: ff.ff_mul(Av, Bv, out=Rv, stream=st),
             "Mul22 (Dekker)": lambda st=stream: ff.ff_mul_dekker(Av, Bv, out=Rv, stream=st),
+            "Add22 (accurate)": lambda st=stream: ff.ff_add_accurate(Av, Bv, out=Rv, stream=st),
         }[op]
 
     # the first n words of each plane: every plane of A[:, :n] is contiguous

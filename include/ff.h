@@ -119,6 +119,24 @@ ff_status ff_div(const float *a_hi, const float *a_lo, const float *b_hi,
                  const float *b_lo, float *r_hi, float *r_lo, int64_t n,
                  void *stream);
 
+/* Cancellation-safe float-float addition and subtraction (not in the
+ * paper): r = a + b (resp. a - b) by the AccurateDWPlusDW algorithm of
+ * Joldes, Muller and Popescu (ACM TOMS 2017):
+ *   (sh, sl) = Add12(a_hi, b_hi); (th, tl) = Add12(a_lo, b_lo);
+ *   c = sl (+) th; (vh, vl) = Fast2Sum(sh, c); w = tl (+) vl;
+ *   (r_hi, r_lo) = Fast2Sum(vh, w).
+ * Its error is relative in every case, |r - (a + b)| <= 3u^2/(1 - 4u)
+ * |a + b| with u = 2^-24, where the paper's Add22 bound (section 4.1,
+ * Add22 theorem) is not relative once the operands cancel; it costs about
+ * twice Add22's operations, which stay far below the HBM bound.
+ * Arguments, layout and errors as for ff_add. */
+ff_status ff_add_accurate(const float *a_hi, const float *a_lo,
+                          const float *b_hi, const float *b_lo, float *r_hi,
+                          float *r_lo, int64_t n, void *stream);
+ff_status ff_sub_accurate(const float *a_hi, const float *a_lo,
+                          const float *b_hi, const float *b_lo, float *r_hi,
+                          float *r_lo, int64_t n, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Batched float-float dot products (reductions)                            */
 /* ------------------------------------------------------------------------ */

@@ -22,6 +22,7 @@ from ._lib import (GEMM_FMA_LOOP, GEMM_SLICED_BF16, GEMM_SLICED_I8, MATVEC_FAST,
 __all__ = [
     "lib", "FFError", "DotCfg", "build_info",
     "ff_add", "ff_sub", "ff_mul", "ff_mul_dekker", "ff_div", "ff_copy",
+    "ff_add_accurate", "ff_sub_accurate",
     "ff_add12", "ff_mul12", "f32_add", "f32_mul", "f32_mad",
     "ff_dot_batched", "ff_dot_ff_batched", "ff_dot_batched_workspace_size",
     "ff_sum_batched", "ff_sum_ff_batched",
@@ -112,6 +113,18 @@ def ff_mul_dekker(a, b, out=None, stream=None):
 def ff_div(a, b, out=None, stream=None):
     """Float-float quotient a / b (Div22, Dekker's div2)."""
     return _elementwise("ff_div", a, b, out, stream)
+
+
+def ff_add_accurate(a, b, out=None, stream=None):
+    """Cancellation-safe float-float sum (AccurateDWPlusDW of Joldes, Muller
+    and Popescu): relative error below 3u^2/(1 - 4u), u = 2^-24, also when
+    a and b cancel."""
+    return _elementwise("ff_add_accurate", a, b, out, stream)
+
+
+def ff_sub_accurate(a, b, out=None, stream=None):
+    """Cancellation-safe float-float difference a - b."""
+    return _elementwise("ff_sub_accurate", a, b, out, stream)
 
 
 def ff_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> torch.Tensor:

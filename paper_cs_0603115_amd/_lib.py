@@ -41,6 +41,8 @@ SIGNATURES = {
     "ff_mul": _EW,
     "ff_mul_dekker": _EW,
     "ff_div": _EW,
+    "ff_add_accurate": _EW,
+    "ff_sub_accurate": _EW,
     "ff_copy": ([_P, _P, _i64, _P], _st),
     "ff_add12": ([_P, _P, _P, _P, _i64, _P], _st),
     "ff_mul12": ([_P, _P, _P, _P, _i64, _P], _st),

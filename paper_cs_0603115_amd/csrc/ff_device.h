@@ -72,6 +72,31 @@ __device__ __forceinline__ void add22(float ah, float al, float bh, float bl,
     add12(r, s, rh, rl);
 }
 
+// Fast2Sum: s = a (+) b and r = b (-) (s (-) a), exact when |a| >= |b|.
+__device__ __forceinline__ void fast_add12(float a, float b, float &s, float &r)
+{
+    s = a + b;
+    const float z = s - a;
+    r = b - z;
+}
+
+// Cancellation-safe addition (not in the paper: its Add22 bound is not
+// relative when the operands cancel).  Joldes, Muller and Popescu's
+// AccurateDWPlusDW (ACM TOMS 2017): the high and the low words are added
+// with exact TwoSums, the low sum is folded into the high one, and two
+// Fast2Sums renormalise; relative error below 3u^2/(1 - 4u), u = 2^-24.
+__device__ __forceinline__ void add22_accurate(float ah, float al, float bh, float bl,
+                                               float &rh, float &rl)
+{
+    float sh, sl, th, tl, vh, vl;
+    add12(ah, bh, sh, sl);
+    add12(al, bl, th, tl);
+    const float c = sl + th;
+    fast_add12(sh, c, vh, vl);
+    const float w = tl + vl;
+    fast_add12(vh, w, rh, rl);
+}
+
 // Mul22 theorem with final step Add12(t1, t3).
 template <bool DEKKER>
 __device__ __forceinline__ void mul22(float ah, float al, float bh, float bl,
@@ -114,7 +139,15 @@ __device__ __forceinline__ void wave_allreduce_add22(float &h, float &l)
 }
 
 // Operator codes shared by the elementwise kernels and the C ABI.
-enum Op : int { OP_ADD = 0, OP_SUB = 1, OP_MUL = 2, OP_MUL_DEKKER = 3, OP_DIV = 4 };
+enum Op : int {
+    OP_ADD = 0,
+    OP_SUB = 1,
+    OP_MUL = 2,
+    OP_MUL_DEKKER = 3,
+    OP_DIV = 4,
+    OP_ADD_ACCURATE = 5,
+    OP_SUB_ACCURATE = 6
+};
 
 template <int OP>
 __device__ __forceinline__ void apply(float ah, float al, float bh, float bl,
@@ -128,8 +161,12 @@ __device__ __forceinline__ void apply(float ah, float al, float bh, float bl,
         mul22<false>(ah, al, bh, bl, rh, rl);
     else if constexpr (OP == OP_MUL_DEKKER)
         mul22<true>(ah, al, bh, bl, rh, rl);
-    else
+    else if constexpr (OP == OP_DIV)
         div22(ah, al, bh, bl, rh, rl);
+    else if constexpr (OP == OP_ADD_ACCURATE)
+        add22_accurate(ah, al, bh, bl, rh, rl);
+    else
+        add22_accurate(ah, al, -bh, -bl, rh, rl);
 }
 
 } // namespace ffd

@@ -24,6 +24,8 @@ struct Sub22 { static constexpr int op = ffd::OP_SUB; };
 struct Mul22 { static constexpr int op = ffd::OP_MUL; };
 struct Mul22Dekker { static constexpr int op = ffd::OP_MUL_DEKKER; };
 struct Div22 { static constexpr int op = ffd::OP_DIV; };
+struct Add22Accurate { static constexpr int op = ffd::OP_ADD_ACCURATE; };
+struct Sub22Accurate { static constexpr int op = ffd::OP_SUB_ACCURATE; };
 
 // Launch shape chosen by a sweep on MI355X over workgroup sizes 256-1024,
 // 1-8 float4 groups per thread, persistent grids, XCD-contiguous tile
@@ -217,6 +219,18 @@ ff_status ff_div(const float *a_hi, const float *a_lo, const float *b_hi, const 
                  float *r_hi, float *r_lo, int64_t n, void *stream)
 {
     return elementwise<Div22>(a_hi, a_lo, b_hi, b_lo, r_hi, r_lo, n, stream);
+}
+
+ff_status ff_add_accurate(const float *a_hi, const float *a_lo, const float *b_hi,
+                          const float *b_lo, float *r_hi, float *r_lo, int64_t n, void *stream)
+{
+    return elementwise<Add22Accurate>(a_hi, a_lo, b_hi, b_lo, r_hi, r_lo, n, stream);
+}
+
+ff_status ff_sub_accurate(const float *a_hi, const float *a_lo, const float *b_hi,
+                          const float *b_lo, float *r_hi, float *r_lo, int64_t n, void *stream)
+{
+    return elementwise<Sub22Accurate>(a_hi, a_lo, b_hi, b_lo, r_hi, r_lo, n, stream);
 }
 
 ff_status ff_copy(const float *src, float *dst, int64_t n, void *stream_ptr)

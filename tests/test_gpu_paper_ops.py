@@ -183,3 +183,18 @@ def test_accuracy_float_float_operators_2p24(op, workload):
     # the theorems' bounds hold for every input (Add22: max(2^-24 |al+bl|,
     # 2^-44 |a+b|); Mul22: 2^-44 relative)
     assert float(ratio.max()) <= 1.0
+
+
+def test_accuracy_cancellation_safe_add_2p24():
+    # the remedy for Add22's non-relative bound: on the cancellation-heavy
+    # workload every result is within 3u^2/(1 - 4u) relative, u = 2^-24
+    ff = _ff()
+    _announce("[gpu] accuracy cancellation-safe add (mixed) over 2^24 random vectors")
+    a, b, _ = fi.mixed_ff_pair(ACC_N, 115025, device="cuda")
+    r = ff.ff_add_accurate(a, b)
+    torch.cuda.synchronize()
+    an, bn, rn = a.cpu().numpy(), b.cpu().numpy(), r.cpu().numpy()
+    rel, _ = oracle.ff_errors("add22", an[0], an[1], bn[0], bn[1], rn[0], rn[1])
+    bound = 3.0 * 2.0 ** -48 / (1.0 - 2.0 ** -22)
+    _report("add22_accurate_mixed", rel, rel / bound)
+    assert float(rel.max()) <= bound
