@@ -21,6 +21,9 @@ them):
   * ``batched_dot``: 4096 vectors, lengths floor(2^U), U ~ U[6, 20]; FP32
     entries normal(0,1) * 2^k, k integer uniform in [-10, 10].
   * ``gaussian_ff``: FP64 normal(0,1) entries split into (hi, lo).
+  * ``ill_conditioned_dot``: binary32 vectors whose dot product cancels to a
+    prescribed condition number (the construction of Ogita, Rump and Oishi's
+    test generator, 2005, section 6, written here from its description).
 """
 from __future__ import annotations
 
@@ -29,6 +32,7 @@ import torch
 __all__ = [
     "split_f64", "base_ff", "mixed_ff_pair", "batched_dot", "gaussian_ff",
     "gaussian_f32", "join_f64", "random_f32", "random_ff", "scaled_normal",
+    "ill_conditioned_dot",
 ]
 
 
@@ -193,3 +197,38 @@ def random_ff(n: int, seed: int, emin: int = -40, emax: int = 40, max_gap: int =
     zero = torch.rand(n, generator=g, device=device) < p_zero_lo
     lo = torch.where(zero, torch.zeros_like(lo), lo)
     return torch.stack([hi, lo])
+
+
+def ill_conditioned_dot(n: int, seed: int, log2_cond: float = 40.0, device="cpu"):
+    """binary32 x, y of length n (n >= 6) whose dot product has condition
+    number 2 sum|x_i y_i| / |x.y| near 2^log2_cond.  The first half holds
+    random entries whose exponents spread over [0, log2_cond / 2]; in the
+    second half, with exponents falling from log2_cond / 2 to 0, each y_i
+    is chosen so that x_i y_i cancels the running sum (kept in FP64) down to
+    a random value of the current magnitude.  The entries are then shuffled.
+    Data generation only: the exact dot product and its condition number
+    are measured by the caller."""
+    if n < 6:
+        raise ValueError("n >= 6")
+    g = _gen(seed, "cpu")
+    half = n // 2
+    b = log2_cond / 2.0
+    e1 = torch.round(torch.rand(half, generator=g, dtype=torch.float64) * b)
+    e1[0], e1[-1] = round(b), 0.0
+    x1 = ((2 * torch.rand(half, generator=g, dtype=torch.float64) - 1) * torch.exp2(e1)).float()
+    y1 = ((2 * torch.rand(half, generator=g, dtype=torch.float64) - 1) * torch.exp2(e1)).float()
+    rest = n - half
+    e2 = torch.round(torch.linspace(b, 0.0, rest, dtype=torch.float64))
+    x2 = ((2 * torch.rand(rest, generator=g, dtype=torch.float64) - 1) * torch.exp2(e2)).float()
+    target = (2 * torch.rand(rest, generator=g, dtype=torch.float64) - 1) * torch.exp2(e2)
+    y2 = torch.empty(rest, dtype=torch.float32)
+    run = float((x1.double() * y1.double()).sum())
+    for i in range(rest):
+        xi = float(x2[i])
+        yi = torch.tensor((float(target[i]) - run) / xi, dtype=torch.float64).float()
+        y2[i] = yi
+        run += xi * float(yi)
+    perm = torch.randperm(n, generator=g)
+    x = torch.cat([x1, x2])[perm].contiguous()
+    y = torch.cat([y1, y2])[perm].contiguous()
+    return x.to(device), y.to(device)

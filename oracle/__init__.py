@@ -75,6 +75,10 @@ _SIGS = {
     "oracle_gemm_ff_seq": ([_i64, _F, _F, _i64, _F, _F, _i64, _F, _F, _i64,
                             _i64, _i64, _i64, _i64], None),
     "oracle_f32_ref": ([_int, _F, _F, _F, _F, _i64], _int),
+    "oracle_sum2": ([_F, _i64, _F], None),
+    "oracle_dot2": ([_F, _F, _i64, _F], None),
+    "oracle_sum2_batched": ([_F, _I64, _i64, _F], None),
+    "oracle_dot2_batched": ([_F, _F, _I64, _i64, _F], None),
     "oracle_ff_errors": ([_int, _F, _F, _F, _F, _F, _F, _i64, _D, _D], _int),
     "oracle_exact_dot": ([_F, _i64, _F, _i64, _i64, _I64], None),
     "oracle_exact_dot_ff": ([_F, _F, _i64, _F, _F, _i64, _i64, _I64], None),
@@ -230,6 +234,40 @@ def elementwise(op: str, ah, al, bh, bl, out=None):
     if rc != 0:
         raise ValueError(op)
     return rh, rl
+
+
+def sum2(x):
+    """Sum2 of Ogita, Rump and Oishi (2005): returns (p, s); the result is
+    the binary32 sum p (+) s."""
+    (x,), n = _pair_inputs(x)
+    out = np.empty(2, np.float32)
+    lib().oracle_sum2(_p(x), n, _p(out))
+    return out[0], out[1]
+
+
+def dot2(x, y):
+    """Dot2 of Ogita, Rump and Oishi (2005), FMA TwoProduct: returns (p, s);
+    the result is p (+) s."""
+    (x, y), n = _pair_inputs(x, y)
+    out = np.empty(2, np.float32)
+    lib().oracle_dot2(_p(x), _p(y), n, _p(out))
+    return out[0], out[1]
+
+
+def sum2_batched(x, offsets):
+    (x,), _ = _pair_inputs(x)
+    offs = np.ascontiguousarray(offsets, dtype=np.int64)
+    out = np.empty(2 * (offs.size - 1), np.float32)
+    lib().oracle_sum2_batched(_p(x), _p(offs), offs.size - 1, _p(out))
+    return out[0::2].copy(), out[1::2].copy()
+
+
+def dot2_batched(x, y, offsets):
+    (x, y), _ = _pair_inputs(x, y)
+    offs = np.ascontiguousarray(offsets, dtype=np.int64)
+    out = np.empty(2 * (offs.size - 1), np.float32)
+    lib().oracle_dot2_batched(_p(x), _p(y), _p(offs), offs.size - 1, _p(out))
+    return out[0::2].copy(), out[1::2].copy()
 
 
 F32_REF_OPS = {"add": 0, "mul": 1, "mad": 2}

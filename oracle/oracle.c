@@ -358,6 +358,67 @@ void oracle_gemm_ff_seq(int64_t K, const float *Ah, const float *Al, int64_t lda
 }
 
 /* ------------------------------------------------------------------------ */
+/* Compensated summation and dot product (Ogita, Rump and Oishi 2005)        */
+/* ------------------------------------------------------------------------ */
+/*
+ * The paper names compensated algorithms as future work (section 7).  These
+ * are the working-precision algorithms Sum2 and Dot2 of Ogita, Rump and
+ * Oishi ("Accurate sum and dot product", SIAM J. Sci. Comput. 26(6), 2005):
+ *   Sum2: p = x_1, s = 0; for i >= 2: (p, q) = TwoSum(p, x_i), s = s (+) q;
+ *   Dot2: (p, s) = TwoProduct(x_1, y_1); for i >= 2:
+ *         (h, r) = TwoProduct(x_i, y_i), (p, q) = TwoSum(p, h),
+ *         s = s (+) (q (+) r);
+ * the result is p (+) s.  TwoProduct is the FMA form.  out2 receives
+ * (p, s), the unevaluated result before its final rounding; n = 0 gives
+ * (0, 0).
+ */
+void oracle_sum2(const float *x, int64_t n, float *out2)
+{
+    float p = 0.0f, s = 0.0f;
+    if (n > 0)
+        p = x[0];
+    for (int64_t i = 1; i < n; ++i) {
+        float q;
+        add12(p, x[i], &p, &q);
+        s = s + q;
+    }
+    out2[0] = p;
+    out2[1] = s;
+}
+
+void oracle_dot2(const float *x, const float *y, int64_t n, float *out2)
+{
+    float p = 0.0f, s = 0.0f;
+    if (n > 0)
+        mul12_fma(x[0], y[0], &p, &s);
+    for (int64_t i = 1; i < n; ++i) {
+        float h, r, q;
+        mul12_fma(x[i], y[i], &h, &r);
+        add12(p, h, &p, &q);
+        s = s + (q + r);
+    }
+    out2[0] = p;
+    out2[1] = s;
+}
+
+/* Batched forms over concatenated vectors (vector v is [offsets[v],
+ * offsets[v+1])); out2 has 2 * nvec entries. */
+void oracle_sum2_batched(const float *x, const int64_t *offsets, int64_t nvec,
+                         float *out2)
+{
+    for (int64_t v = 0; v < nvec; ++v)
+        oracle_sum2(x + offsets[v], offsets[v + 1] - offsets[v], out2 + 2 * v);
+}
+
+void oracle_dot2_batched(const float *x, const float *y, const int64_t *offsets,
+                         int64_t nvec, float *out2)
+{
+    for (int64_t v = 0; v < nvec; ++v)
+        oracle_dot2(x + offsets[v], y + offsets[v], offsets[v + 1] - offsets[v],
+                    out2 + 2 * v);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Exact accumulation: a long fixed-point accumulator                       */
 /* ------------------------------------------------------------------------ */
 /*

@@ -13,6 +13,7 @@ import pytest
 import oracle
 import test_oracle_operators as OPS
 import test_oracle_accurate_add as ACC
+import test_oracle_compensated as CMP
 import test_oracle_paper_tables as TAB
 import test_oracle_primitives as PRIM
 import test_oracle_reductions as RED
@@ -59,6 +60,14 @@ ACC_PINS = [
     lambda: ACC.test_relative_error_bound_holds_under_cancellation("random"),
     lambda: ACC.test_relative_error_bound_holds_under_cancellation("gap"),
 ]
+CMP_PINS = [
+    CMP.test_empty_and_single_terms,
+    CMP.test_integer_data_is_exact,
+    lambda: CMP.test_dot2_error_bound_ill_conditioned(25),
+    lambda: CMP.test_dot2_error_bound_ill_conditioned(40),
+    CMP.test_dot2_where_the_naive_sum_fails,
+    lambda: CMP.test_sum2_error_bound_random(3000),
+]
 
 # (name, original text, planted text, pins expected to catch it)
 MUTATIONS = [
@@ -90,6 +99,11 @@ MUTATIONS = [
     ("accurate_sign", "    float c = sl + th;", "    float c = sl - th;", ACC_PINS),
     ("accurate_low_pair", "    add12(al, bl, &th, &tl);", "    add12(al, bh, &th, &tl);", ACC_PINS),
     ("accurate_final_order", "    fast_add12(vh, w, rh, rl);", "    fast_add12(w, vh, rh, rl);", ACC_PINS),
+    ("dot2_dropped_product_error", "        s = s + (q + r);", "        s = s + q;", CMP_PINS),
+    ("dot2_dropped_sum_error", "        s = s + (q + r);", "        s = s + r;", CMP_PINS),
+    ("sum2_dropped_error", "        s = s + q;\n    }\n    out2[0] = p;\n    out2[1] = s;\n}\n\nvoid oracle_dot2",
+     "        s = s + 0.0f * q;\n    }\n    out2[0] = p;\n    out2[1] = s;\n}\n\nvoid oracle_dot2", CMP_PINS),
+    ("dot2_first_term_error", "        mul12_fma(x[0], y[0], &p, &s);", "        { mul12_fma(x[0], y[0], &p, &s); s = 0.0f; }", CMP_PINS),
     ("mad_unfused", "r[i] = fmaf(a[i], b[i], c[i]);", "r[i] = a[i] * b[i] + c[i];",
      TAB_PINS),
     ("errors_dropped_low_word", "            la_add_f32(&exact, bl[i], 1);\n            la_add_f32(&lo, al[i], 1);",
