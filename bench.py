@@ -123,9 +123,14 @@ def secondary(stream) -> dict:
     ms = _time_launches(lambda: ff.ff_dot_batched(x, y, offs, cfg=cfg, out=res, workspace=ws,
                                                   stream=stream), 10, stream)
     gbs = 8 * total / (ms * 1e-3) / 1e9
+    ms2 = _time_launches(lambda: ff.ff_dot2_batched(x, y, offs, cfg=cfg, out=res, workspace=ws,
+                                                    stream=stream), 10, stream)
+    gbs2 = 8 * total / (ms2 * 1e-3) / 1e9
     out["dot_batched"] = {"elements": total, "ms": round(ms, 4), "elements/s": total / (ms * 1e-3),
                           "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                          "cfg": list(cfg)}
+                          "cfg": list(cfg),
+                          "dot2_compensated": {"ms": round(ms2, 4), "GB/s": round(gbs2, 1),
+                                               "hbm_frac": round(gbs2 / HBM_PEAK_GBS, 4)}}
     del x, y, offs, res, ws
     torch.cuda.empty_cache()
 

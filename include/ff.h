@@ -219,6 +219,29 @@ ff_status ff_sum_ff_batched(const float *x_hi, const float *x_lo,
                             size_t ws_bytes, float *out_hi, float *out_lo,
                             void *stream);
 
+/* Compensated batched dot products and sums (the paper's named future work,
+ * section 7): Dot2 and Sum2 of Ogita, Rump and Oishi (SIAM J. Sci. Comput.
+ * 2005) on binary32 inputs.  Each vector keeps a running binary32 sum p and
+ * adds the exact rounding error of every step (TwoSum) and every product
+ * (TwoProduct, FMA form) into a second binary32 word s; chunk partials
+ * (p, s) merge as (p, q) = TwoSum(p1, p2), s = (s1 + s2) + q.  The result
+ * is returned as Add12(p, s): out_hi[v] is the algorithm's binary32 result
+ * p (+) s, out_lo[v] the remainder.  Error: |out_hi - x.y| <= u |x.y| +
+ * gamma_n^2 sum |x_i y_i| (u = 2^-24, gamma_n = n u / (1 - n u)), the
+ * accuracy of the working precision squared; fewer operations per term than
+ * float-float accumulation (no renormalisation per step).  Same execution,
+ * workspace, launch shape, arguments and errors as ff_dot_batched /
+ * ff_sum_batched (ff_dot_batched_workspace_size applies). */
+ff_status ff_dot2_batched(const float *x, const float *y,
+                          const int64_t *offsets, int32_t nvec,
+                          int64_t total_len, const ff_dot_cfg *cfg, void *ws,
+                          size_t ws_bytes, float *out_hi, float *out_lo,
+                          void *stream);
+ff_status ff_sum2_batched(const float *x, const int64_t *offsets, int32_t nvec,
+                          int64_t total_len, const ff_dot_cfg *cfg, void *ws,
+                          size_t ws_bytes, float *out_hi, float *out_lo,
+                          void *stream);
+
 /* Launch-shape autotuner for ff_dot_batched on this batch: times every
  * candidate (block 256/512 x unroll 1/2/4/8 x chunk 4096..65536 x 2..16
  * workgroups per compute unit) whose workspace fits in ws_bytes, `reps`

@@ -25,7 +25,7 @@ __all__ = [
     "ff_add_accurate", "ff_sub_accurate",
     "ff_add12", "ff_mul12", "f32_add", "f32_mul", "f32_mad",
     "ff_dot_batched", "ff_dot_ff_batched", "ff_dot_batched_workspace_size",
-    "ff_sum_batched", "ff_sum_ff_batched",
+    "ff_sum_batched", "ff_sum_ff_batched", "ff_dot2_batched", "ff_sum2_batched",
     "ff_matvec", "ff_matvec_backward", "ff_dot_backward", "MATVEC_FAST", "MATVEC_PLAIN",
     "ff_gemm", "ff_gemm_workspace_size", "GEMM_FMA_LOOP", "GEMM_SLICED_BF16", "GEMM_SLICED_I8",
     "ff_empty", "ff_zeros",
@@ -275,6 +275,48 @@ def ff_dot_batched(x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, cfg=
             ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
             ctypes.c_void_p(offsets.data_ptr()), nvec, x.numel(), _cfg_ptr(cfg),
             ctypes.c_void_p(ws.data_ptr()), ws.numel(), oh, ol, _stream_handle(stream)))
+    return out
+
+
+def ff_dot2_batched(x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, cfg=None,
+                    out=None, workspace=None, stream=None) -> torch.Tensor:
+    """Compensated dots (Dot2 of Ogita, Rump and Oishi) of binary32 vectors:
+    out[0, v] is the binary32 Dot2 result of [offsets[v], offsets[v+1]),
+    out[1, v] the remainder of its final rounding.  Returns (2, nvec)."""
+    for t, name in ((x, "x"), (y, "y")):
+        if t.dtype != torch.float32 or t.dim() != 1 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError(f"{name}: contiguous float32 vector on a HIP device expected")
+    if x.numel() != y.numel():
+        raise ValueError("x and y differ in length")
+    nvec = _check_offsets(offsets, x.device)
+    out = ff_empty((nvec,), device=x.device) if out is None else out
+    _check_ff(out, "out")
+    ws = _workspace(ff_dot_batched_workspace_size(x.numel(), nvec, cfg), x.device, workspace)
+    oh, ol = _planes(out)
+    with torch.cuda.device(x.device):
+        check("ff_dot2_batched", lib.ff_dot2_batched(
+            ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+            ctypes.c_void_p(offsets.data_ptr()), nvec, x.numel(), _cfg_ptr(cfg),
+            ctypes.c_void_p(ws.data_ptr()), ws.numel(), oh, ol, _stream_handle(stream)))
+    return out
+
+
+def ff_sum2_batched(x: torch.Tensor, offsets: torch.Tensor, cfg=None, out=None, workspace=None,
+                    stream=None) -> torch.Tensor:
+    """Compensated sums (Sum2 of Ogita, Rump and Oishi) of binary32
+    segments; same result layout as ff_dot2_batched."""
+    if x.dtype != torch.float32 or x.dim() != 1 or not x.is_contiguous() or not x.is_cuda:
+        raise ValueError("x: contiguous float32 vector on a HIP device expected")
+    nvec = _check_offsets(offsets, x.device)
+    out = ff_empty((nvec,), device=x.device) if out is None else out
+    _check_ff(out, "out")
+    ws = _workspace(ff_dot_batched_workspace_size(x.numel(), nvec, cfg), x.device, workspace)
+    oh, ol = _planes(out)
+    with torch.cuda.device(x.device):
+        check("ff_sum2_batched", lib.ff_sum2_batched(
+            ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), nvec, x.numel(),
+            _cfg_ptr(cfg), ctypes.c_void_p(ws.data_ptr()), ws.numel(), oh, ol,
+            _stream_handle(stream)))
     return out
 
 

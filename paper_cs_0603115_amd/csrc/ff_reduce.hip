@@ -164,8 +164,57 @@ __global__ __launch_bounds__(256) void dot_ranges(const int64_t *__restrict__ of
     }
 }
 
-// One wavefront per vector: Add22 of the vector's chunk partials, lane-
-// strided in chunk order, then a butterfly; (0, 0) for an empty vector.
+// Accumulation policies.  A partial is a pair of binary32 words (h, l).
+// AccFF: float-float accumulation, every term and every partial added with
+// Add22 (section 4.1); the pair is the result.
+struct AccFF {
+    __device__ __forceinline__ static void add(float &h, float &l, float ph, float pl)
+    {
+        ffd::add22(h, l, ph, pl, h, l);
+    }
+    __device__ __forceinline__ static void merge(float &h, float &l, float oh, float ol)
+    {
+        ffd::add22(h, l, oh, ol, h, l);
+    }
+    __device__ __forceinline__ static void finish(float &, float &) {}
+};
+// AccComp: compensated accumulation (Sum2 / Dot2 of Ogita, Rump and Oishi,
+// 2005): h is a running binary32 sum whose TwoSum rounding errors, and the
+// terms' low words, are added in binary32 into l.  Two partials merge the
+// same way (symmetric in its operands, so a butterfly leaves every lane with
+// the same bits).  The result is Add12(h, l): its high word is the
+// algorithm's rounded result h (+) l.
+struct AccComp {
+    __device__ __forceinline__ static void add(float &h, float &l, float ph, float pl)
+    {
+        float q;
+        ffd::add12(h, ph, h, q);
+        l = l + (q + pl);
+    }
+    __device__ __forceinline__ static void merge(float &h, float &l, float oh, float ol)
+    {
+        float q;
+        ffd::add12(h, oh, h, q);
+        l = (l + ol) + q;
+    }
+    __device__ __forceinline__ static void finish(float &h, float &l) { ffd::add12(h, l, h, l); }
+};
+
+// Butterfly all-reduce of a partial over the 64 lanes of a wavefront.
+template <class Acc>
+__device__ __forceinline__ void wave_allreduce(float &h, float &l)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const float oh = __shfl_xor(h, m, 64);
+        const float ol = __shfl_xor(l, m, 64);
+        Acc::merge(h, l, oh, ol);
+    }
+}
+
+// One wavefront per vector: the vector's chunk partials merged lane-strided
+// in chunk order, then a butterfly; (0, 0) for an empty vector.
+template <class Acc>
 __global__ __launch_bounds__(256) void dot_combine(int32_t nvec, Workspace w,
                                                    float *__restrict__ out_hi,
                                                    float *__restrict__ out_lo)
@@ -180,9 +229,10 @@ __global__ __launch_bounds__(256) void dot_combine(int32_t nvec, Workspace w,
     float h = 0.0f, l = 0.0f;
     for (int64_t c = c0 + lane; c < c1; c += 64) {
         const float2 p = w.partials[c];
-        ffd::add22(h, l, p.x, p.y, h, l);
+        Acc::merge(h, l, p.x, p.y);
     }
-    ffd::wave_allreduce_add22(h, l);
+    wave_allreduce<Acc>(h, l);
+    Acc::finish(h, l);
     if (lane == 0) {
         out_hi[v] = h;
         out_lo[v] = l;
@@ -190,9 +240,9 @@ __global__ __launch_bounds__(256) void dot_combine(int32_t nvec, Workspace w,
 }
 
 // Input kinds.  Terms<In> loads the float4 group g (elements 4g .. 4g+3)
-// of every input plane into a Group, and adds its four exact terms to four
-// float-float accumulators; the masked form zeroes the terms whose element
-// lies outside [s, e) (a zero term leaves an Add22 accumulator unchanged).
+// of every input plane, and forms each element's exact term as a pair
+// (TwoProd of binary32 inputs, Mul22 of float-float inputs, the value
+// itself for sums).
 struct InF32 {
     const float *x, *y;
 };
@@ -205,11 +255,6 @@ struct InSumF32 {
 struct InSumFF {
     const float *xh, *xl;
 };
-
-__device__ __forceinline__ void accumulate_term(float &h, float &l, float ph, float pl)
-{
-    ffd::add22(h, l, ph, pl, h, l);
-}
 
 template <int P>
 struct Planes {
@@ -300,14 +345,14 @@ struct Terms<InSumFF> {
     }
 };
 
-template <class In>
+template <class In, class Acc>
 __device__ __forceinline__ void add_group(const typename Terms<In>::G &q, float2 acc[4])
 {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         float ph, pl;
         Terms<In>::term(q, k, ph, pl);
-        accumulate_term(acc[k].x, acc[k].y, ph, pl);
+        Acc::add(acc[k].x, acc[k].y, ph, pl);
     }
 }
 
@@ -317,7 +362,7 @@ __device__ __forceinline__ void add_group(const typename Terms<In>::G &q, float2
 // arithmetic; the at most 3 + 3 elements before the first and after the
 // last whole group are read one by one.  Otherwise every element is read
 // on its own.
-template <class In, int BLOCK, int UNROLL, bool VEC>
+template <class In, class Acc, int BLOCK, int UNROLL, bool VEC>
 __global__ __launch_bounds__(BLOCK) void dot_partials(In in, Workspace w, int32_t nvec)
 {
     constexpr int kWaves = BLOCK / 64;
@@ -351,10 +396,10 @@ __global__ __launch_bounds__(BLOCK) void dot_partials(In in, Workspace w, int32_
                     q[u] = Terms<In>::load(in, g + u * BLOCK);
 #pragma unroll
                 for (int u = 0; u < UNROLL; ++u)
-                    add_group<In>(q[u], acc);
+                    add_group<In, Acc>(q[u], acc);
             }
             for (; g < gb; g += BLOCK)
-                add_group<In>(Terms<In>::load(in, g), acc);
+                add_group<In, Acc>(Terms<In>::load(in, g), acc);
             // head [s, 4 ga) and tail [4 gb, e) elements, by threads 0..2
             // and 64..66 (when a chunk lies inside one group, gb = ga and
             // the head covers it)
@@ -368,21 +413,21 @@ __global__ __launch_bounds__(BLOCK) void dot_partials(In in, Workspace w, int32_
             if (i >= 0) {
                 float ph, pl;
                 Terms<In>::one(in, i, ph, pl);
-                accumulate_term(acc[0].x, acc[0].y, ph, pl);
+                Acc::add(acc[0].x, acc[0].y, ph, pl);
             }
         } else {
             for (int64_t i = s + tid; i < e; i += BLOCK) {
                 float ph, pl;
                 Terms<In>::one(in, i, ph, pl);
-                accumulate_term(acc[0].x, acc[0].y, ph, pl);
+                Acc::add(acc[0].x, acc[0].y, ph, pl);
             }
         }
         float h = acc[0].x, l = acc[0].y;
-        ffd::add22(h, l, acc[1].x, acc[1].y, h, l);
+        Acc::merge(h, l, acc[1].x, acc[1].y);
         float h2 = acc[2].x, l2 = acc[2].y;
-        ffd::add22(h2, l2, acc[3].x, acc[3].y, h2, l2);
-        ffd::add22(h, l, h2, l2, h, l);
-        ffd::wave_allreduce_add22(h, l);
+        Acc::merge(h2, l2, acc[3].x, acc[3].y);
+        Acc::merge(h, l, h2, l2);
+        wave_allreduce<Acc>(h, l);
         if (lane == 0)
             wave_part[wave] = make_float2(h, l);
         __syncthreads();
@@ -390,7 +435,7 @@ __global__ __launch_bounds__(BLOCK) void dot_partials(In in, Workspace w, int32_
             float th = wave_part[0].x, tl = wave_part[0].y;
 #pragma unroll
             for (int k = 1; k < kWaves; ++k)
-                ffd::add22(th, tl, wave_part[k].x, wave_part[k].y, th, tl);
+                Acc::merge(th, tl, wave_part[k].x, wave_part[k].y);
             w.partials[c] = make_float2(th, tl);
         }
         __syncthreads();
@@ -438,19 +483,19 @@ int default_grid()
     return 2 * (cus > 0 ? cus : 256);
 }
 
-template <class In, int BLOCK, int UNROLL>
+template <class In, class Acc, int BLOCK, int UNROLL>
 void launch_partials(bool vec, int grid, hipStream_t st, const In &in, const Workspace &w,
                      int32_t nvec)
 {
     if (vec)
-        hipLaunchKernelGGL((dot_partials<In, BLOCK, UNROLL, true>), dim3(grid), dim3(BLOCK), 0,
-                           st, in, w, nvec);
+        hipLaunchKernelGGL((dot_partials<In, Acc, BLOCK, UNROLL, true>), dim3(grid), dim3(BLOCK),
+                           0, st, in, w, nvec);
     else
-        hipLaunchKernelGGL((dot_partials<In, BLOCK, 1, false>), dim3(grid), dim3(BLOCK), 0, st,
-                           in, w, nvec);
+        hipLaunchKernelGGL((dot_partials<In, Acc, BLOCK, 1, false>), dim3(grid), dim3(BLOCK), 0,
+                           st, in, w, nvec);
 }
 
-template <class In>
+template <class In, class Acc = AccFF>
 ff_status dot_batched_entry(const In &in, bool vec, const int64_t *offsets, int32_t nvec,
                             int64_t total, const ff_dot_cfg *cfg_in, void *ws, size_t ws_bytes,
                             float *out_hi, float *out_lo, void *stream_ptr)
@@ -476,7 +521,7 @@ ff_status dot_batched_entry(const In &in, bool vec, const int64_t *offsets, int3
                        cfg.chunk, w);
     hipLaunchKernelGGL(dot_ranges, dim3(wave_blocks), dim3(256), 0, st, offsets, nvec, total,
                        cfg.chunk, w);
-#define FF_DOT_LAUNCH(B, U) launch_partials<In, B, U>(vec, grid, st, in, w, nvec)
+#define FF_DOT_LAUNCH(B, U) launch_partials<In, Acc, B, U>(vec, grid, st, in, w, nvec)
     if (cfg.block == 256) {
         switch (cfg.unroll) {
         case 1: FF_DOT_LAUNCH(256, 1); break;
@@ -493,7 +538,8 @@ ff_status dot_batched_entry(const In &in, bool vec, const int64_t *offsets, int3
         }
     }
 #undef FF_DOT_LAUNCH
-    hipLaunchKernelGGL(dot_combine, dim3(wave_blocks), dim3(256), 0, st, nvec, w, out_hi, out_lo);
+    hipLaunchKernelGGL(dot_combine<Acc>, dim3(wave_blocks), dim3(256), 0, st, nvec, w, out_hi,
+                       out_lo);
     return ffh::launch_status();
 }
 
@@ -573,6 +619,36 @@ ff_status ff_sum_ff_batched(const float *x_hi, const float *x_lo, const int64_t 
     const bool vec = ffh::aligned(x_hi, 16) && ffh::aligned(x_lo, 16);
     return dot_batched_entry(InSumFF{x_hi, x_lo}, vec, offsets, nvec, total_len, cfg, ws, ws_bytes,
                              out_hi, out_lo, stream);
+}
+
+ff_status ff_dot2_batched(const float *x, const float *y, const int64_t *offsets, int32_t nvec,
+                          int64_t total_len, const ff_dot_cfg *cfg, void *ws, size_t ws_bytes,
+                          float *out_hi, float *out_lo, void *stream)
+{
+    if (nvec < 0 || total_len < 0)
+        return FF_ERR_SIZE;
+    if (total_len > 0 && (!x || !y))
+        return FF_ERR_NULL;
+    if (!ffh::aligned(x, 4) || !ffh::aligned(y, 4))
+        return FF_ERR_ALIGN;
+    const bool vec = ffh::aligned(x, 16) && ffh::aligned(y, 16);
+    return dot_batched_entry<InF32, AccComp>(InF32{x, y}, vec, offsets, nvec, total_len, cfg, ws,
+                                             ws_bytes, out_hi, out_lo, stream);
+}
+
+ff_status ff_sum2_batched(const float *x, const int64_t *offsets, int32_t nvec,
+                          int64_t total_len, const ff_dot_cfg *cfg, void *ws, size_t ws_bytes,
+                          float *out_hi, float *out_lo, void *stream)
+{
+    if (nvec < 0 || total_len < 0)
+        return FF_ERR_SIZE;
+    if (total_len > 0 && !x)
+        return FF_ERR_NULL;
+    if (!ffh::aligned(x, 4))
+        return FF_ERR_ALIGN;
+    return dot_batched_entry<InSumF32, AccComp>(InSumF32{x}, ffh::aligned(x, 16), offsets, nvec,
+                                                total_len, cfg, ws, ws_bytes, out_hi, out_lo,
+                                                stream);
 }
 
 ff_status ff_dot_batched_autotune(const float *x, const float *y, const int64_t *offsets,

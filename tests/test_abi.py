@@ -144,10 +144,12 @@ def test_dot_workspace_size():
     assert size(1 << 24, 4, (256, 64, 0, 1)) > size(1 << 24, 4, (256, 16384, 0, 1))
 
 
-@pytest.mark.parametrize("name", ["ff_dot_batched", "ff_dot_ff_batched"])
+@pytest.mark.parametrize("name", ["ff_dot_batched", "ff_dot_ff_batched", "ff_dot2_batched",
+                                  "ff_sum_batched", "ff_sum2_batched"])
 def test_dot_validation(name):
     fn = getattr(ff.lib, name)
-    nplanes = 2 if name == "ff_dot_batched" else 4
+    nplanes = {"ff_dot_batched": 2, "ff_dot2_batched": 2, "ff_dot_ff_batched": 4,
+               "ff_sum_batched": 1, "ff_sum2_batched": 1}[name]
     planes = [4096 * (k + 1) for k in range(nplanes)]
     offs, oh, ol, ws = 1 << 20, 2 << 20, 3 << 20, 4 << 20
     need = ff.ff_dot_batched_workspace_size(1000, 8)
