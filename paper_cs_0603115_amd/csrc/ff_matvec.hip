@@ -27,6 +27,12 @@ constexpr int kRowBlock = 256;
 constexpr int kColBlock = 256;
 constexpr int64_t kBandRows = 64;
 
+// Fast forward for kRowsPerGroup rows at a time: the rows share each load
+// of x, and each lane issues the loads of kRowUnroll float4 groups (both
+// rows' planes and x) before any arithmetic.
+constexpr int kRowsPerGroup = 2;
+constexpr int kRowUnroll = 2;
+
 template <int BLOCK, bool VEC>
 __global__ __launch_bounds__(BLOCK) void matvec_rows(int64_t M, int64_t N,
                                                      const float *__restrict__ Ah,
@@ -36,55 +42,96 @@ __global__ __launch_bounds__(BLOCK) void matvec_rows(int64_t M, int64_t N,
                                                      float *__restrict__ yh, float *__restrict__ yl)
 {
     constexpr int kWaves = BLOCK / 64;
-    __shared__ float2 part[kWaves];
+    constexpr int R = kRowsPerGroup, U = kRowUnroll;
+    __shared__ float2 part[R][kWaves];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int64_t r = blockIdx.x; r < M; r += gridDim.x) {
-        const float *rh = Ah + r * lda;
-        const float *rl = Al + r * lda;
-        float2 acc[4];
+    for (int64_t r0 = static_cast<int64_t>(blockIdx.x) * R; r0 < M;
+         r0 += static_cast<int64_t>(gridDim.x) * R) {
+        // rows r0 .. r0 + R - 1; a row beyond M repeats row r0 (not stored)
+        const float *rh[R], *rl[R];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            acc[k] = make_float2(0.0f, 0.0f);
+        for (int q = 0; q < R; ++q) {
+            const int64_t r = (r0 + q < M) ? r0 + q : r0;
+            rh[q] = Ah + r * lda;
+            rl[q] = Al + r * lda;
+        }
+        float2 acc[R][4];
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                acc[q][k] = make_float2(0.0f, 0.0f);
+        auto add_term = [&](int q, int k, float ah, float al, float bh, float bl) {
+            float ph, pl;
+            ffd::mul22<false>(ah, al, bh, bl, ph, pl);
+            ffd::add22(acc[q][k].x, acc[q][k].y, ph, pl, acc[q][k].x, acc[q][k].y);
+        };
         int64_t j_scalar = tid;
         if (VEC) {
             const int64_t ng = N >> 2;
-            const f32x4 *rh4 = reinterpret_cast<const f32x4 *>(rh);
-            const f32x4 *rl4 = reinterpret_cast<const f32x4 *>(rl);
             const f32x4 *xh4 = reinterpret_cast<const f32x4 *>(xh);
             const f32x4 *xl4 = reinterpret_cast<const f32x4 *>(xl);
-            for (int64_t g = tid; g < ng; g += BLOCK) {
-                const f32x4 ah = __builtin_nontemporal_load(rh4 + g);
-                const f32x4 al = __builtin_nontemporal_load(rl4 + g);
+            int64_t g = tid;
+            for (; g + (U - 1) * BLOCK < ng; g += U * BLOCK) {
+                f32x4 bh[U], bl[U], ah[R][U], al[R][U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    bh[u] = xh4[g + u * BLOCK];
+                    bl[u] = xl4[g + u * BLOCK];
+#pragma unroll
+                    for (int q = 0; q < R; ++q) {
+                        ah[q][u] = __builtin_nontemporal_load(
+                            reinterpret_cast<const f32x4 *>(rh[q]) + g + u * BLOCK);
+                        al[q][u] = __builtin_nontemporal_load(
+                            reinterpret_cast<const f32x4 *>(rl[q]) + g + u * BLOCK);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int q = 0; q < R; ++q)
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            add_term(q, k, ah[q][u][k], al[q][u][k], bh[u][k], bl[u][k]);
+            }
+            for (; g < ng; g += BLOCK) {
                 const f32x4 bh = xh4[g], bl = xl4[g];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    float ph, pl;
-                    ffd::mul22<false>(ah[k], al[k], bh[k], bl[k], ph, pl);
-                    ffd::add22(acc[k].x, acc[k].y, ph, pl, acc[k].x, acc[k].y);
+                for (int q = 0; q < R; ++q) {
+                    const f32x4 ah = __builtin_nontemporal_load(
+                        reinterpret_cast<const f32x4 *>(rh[q]) + g);
+                    const f32x4 al = __builtin_nontemporal_load(
+                        reinterpret_cast<const f32x4 *>(rl[q]) + g);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        add_term(q, k, ah[k], al[k], bh[k], bl[k]);
                 }
             }
             j_scalar = 4 * ng + tid;
         }
         for (int64_t j = j_scalar; j < N; j += BLOCK) {
-            float ph, pl;
-            ffd::mul22<false>(rh[j], rl[j], xh[j], xl[j], ph, pl);
-            ffd::add22(acc[0].x, acc[0].y, ph, pl, acc[0].x, acc[0].y);
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+                add_term(q, 0, rh[q][j], rl[q][j], xh[j], xl[j]);
         }
-        float h = acc[0].x, l = acc[0].y, h2 = acc[2].x, l2 = acc[2].y;
-        ffd::add22(h, l, acc[1].x, acc[1].y, h, l);
-        ffd::add22(h2, l2, acc[3].x, acc[3].y, h2, l2);
-        ffd::add22(h, l, h2, l2, h, l);
-        ffd::wave_allreduce_add22(h, l);
-        if (lane == 0)
-            part[wave] = make_float2(h, l);
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            float h = acc[q][0].x, l = acc[q][0].y, h2 = acc[q][2].x, l2 = acc[q][2].y;
+            ffd::add22(h, l, acc[q][1].x, acc[q][1].y, h, l);
+            ffd::add22(h2, l2, acc[q][3].x, acc[q][3].y, h2, l2);
+            ffd::add22(h, l, h2, l2, h, l);
+            ffd::wave_allreduce_add22(h, l);
+            if (lane == 0)
+                part[q][wave] = make_float2(h, l);
+        }
         __syncthreads();
-        if (tid == 0) {
-            float th = part[0].x, tl = part[0].y;
+        if (tid < R && r0 + tid < M) {
+            float th = part[tid][0].x, tl = part[tid][0].y;
 #pragma unroll
             for (int k = 1; k < kWaves; ++k)
-                ffd::add22(th, tl, part[k].x, part[k].y, th, tl);
-            yh[r] = th;
-            yl[r] = tl;
+                ffd::add22(th, tl, part[tid][k].x, part[tid][k].y, th, tl);
+            yh[r0 + tid] = th;
+            yl[r0 + tid] = tl;
         }
         __syncthreads();
     }
@@ -334,11 +381,13 @@ ff_status ff_matvec(int64_t M, int64_t N, const float *A_hi, const float *A_lo, 
     } else {
         const bool vec = all_aligned({A_hi, A_lo, x_hi, x_lo}, 16) && lda % 4 == 0;
         if (vec)
-            hipLaunchKernelGGL((matvec_rows<kRowBlock, true>), dim3(static_cast<unsigned>(M)),
+            hipLaunchKernelGGL((matvec_rows<kRowBlock, true>),
+                               dim3(static_cast<unsigned>(ffh::cdiv(M, kRowsPerGroup))),
                                dim3(kRowBlock), 0, st, M, N, A_hi, A_lo, lda, x_hi, x_lo, y_hi,
                                y_lo);
         else
-            hipLaunchKernelGGL((matvec_rows<kRowBlock, false>), dim3(static_cast<unsigned>(M)),
+            hipLaunchKernelGGL((matvec_rows<kRowBlock, false>),
+                               dim3(static_cast<unsigned>(ffh::cdiv(M, kRowsPerGroup))),
                                dim3(kRowBlock), 0, st, M, N, A_hi, A_lo, lda, x_hi, x_lo, y_hi,
                                y_lo);
     }
