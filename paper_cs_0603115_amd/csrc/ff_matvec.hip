@@ -181,23 +181,10 @@ __global__ __launch_bounds__(BLOCK) void matvec_bwd_band(
             x_l[k] = xl[c0 + k];
         }
     }
-    for (int64_t i = i0; i < i1; ++i) {
+    // rows in pairs: both rows' loads are issued before any arithmetic
+    constexpr int kRowPair = 2;
+    auto row = [&](int64_t i, const float (&a_h)[COLS], const float (&a_l)[COLS]) {
         const float g_h = gh[i], g_l = gl[i];
-        float a_h[COLS], a_l[COLS];
-        if (WANT_DX) {
-            if constexpr (COLS == 4) {
-                const f32x4 vh = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Ah + i * lda + c0));
-                const f32x4 vl = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Al + i * lda + c0));
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    a_h[k] = vh[k];
-                    a_l[k] = vl[k];
-                }
-            } else {
-                a_h[0] = Ah[i * lda + c0];
-                a_l[0] = Al[i * lda + c0];
-            }
-        }
         if (WANT_DA) {
             float d_h[COLS], d_l[COLS];
 #pragma unroll
@@ -221,6 +208,37 @@ __global__ __launch_bounds__(BLOCK) void matvec_bwd_band(
                 ffd::add22(acc[k].x, acc[k].y, ph, pl, acc[k].x, acc[k].y);
             }
         }
+    };
+    auto load_row = [&](int64_t i, float (&a_h)[COLS], float (&a_l)[COLS]) {
+        if (WANT_DX) {
+            if constexpr (COLS == 4) {
+                const f32x4 vh = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Ah + i * lda + c0));
+                const f32x4 vl = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(Al + i * lda + c0));
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    a_h[k] = vh[k];
+                    a_l[k] = vl[k];
+                }
+            } else {
+                a_h[0] = Ah[i * lda + c0];
+                a_l[0] = Al[i * lda + c0];
+            }
+        }
+    };
+    int64_t i = i0;
+    for (; i + kRowPair <= i1; i += kRowPair) {
+        float a_h[kRowPair][COLS], a_l[kRowPair][COLS];
+#pragma unroll
+        for (int p = 0; p < kRowPair; ++p)
+            load_row(i + p, a_h[p], a_l[p]);
+#pragma unroll
+        for (int p = 0; p < kRowPair; ++p)
+            row(i + p, a_h[p], a_l[p]);
+    }
+    for (; i < i1; ++i) {
+        float a_h[COLS], a_l[COLS];
+        load_row(i, a_h, a_l);
+        row(i, a_h, a_l);
     }
     if (WANT_DX) {
 #pragma unroll
