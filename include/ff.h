@@ -152,10 +152,9 @@ ff_status ff_sub_accurate(const float *a_hi, const float *a_lo,
  * their scan), one writing each chunk's element range, ONE persistent
  * launch that walks all chunks of all vectors, and one combining each
  * vector's partials.  Each chunk of `cfg->chunk` elements is reduced by one
- * workgroup (per-lane float-float accumulators, a wavefront butterfly of
- * Add22 over lane shuffles, then the wavefronts' partials in order through
- * LDS) into a float-float partial; one wavefront per vector then adds the
- * vector's partials with an Add22 tree of fixed shape.  No atomics are
+ * wavefront (per-lane float-float accumulators, then a butterfly of Add22
+ * over lane shuffles) into a float-float partial; one wavefront per vector
+ * then adds the vector's partials with an Add22 tree of fixed shape.  No atomics are
  * used: for a given cfg the result is bitwise reproducible run to run.
  * Different cfg values may give different (equally valid) last bits.
  *
@@ -167,8 +166,8 @@ ff_status ff_sub_accurate(const float *a_hi, const float *a_lo,
 typedef struct ff_dot_cfg {
     int32_t block;  /* threads per workgroup: 256 or 512 (0: 512)           */
     int32_t chunk;  /* elements per chunk, a multiple of 4, >= 64 (0: 16384) */
-    int32_t grid;   /* persistent workgroups; 0: 2 per compute unit          */
-    int32_t unroll; /* float4 groups per lane per step: 1, 2, 4, 8 (0: 2)   */
+    int32_t grid;   /* persistent workgroups; 0: 8 per compute unit          */
+    int32_t unroll; /* float4 groups per lane per step: 1, 2, 4, 8 (0: 8)   */
 } ff_dot_cfg;
 
 /* Bytes of device workspace ff_dot_batched / ff_dot_ff_batched need for
@@ -243,7 +242,7 @@ ff_status ff_sum2_batched(const float *x, const int64_t *offsets, int32_t nvec,
                           void *stream);
 
 /* Launch-shape autotuner for ff_dot_batched on this batch: times every
- * candidate (block 256/512 x unroll 1/2/4/8 x chunk 4096..65536 x 2..16
+ * candidate (block 256/512 x unroll 1/2/4/8 x chunk 1024..32768 x 2..16
  * workgroups per compute unit) whose workspace fits in ws_bytes, `reps`
  * launches each after one untimed launch, with HIP events on `stream`, and
  * returns the fastest in *best with its mean time in *best_ms.  SYNCHRONOUS:

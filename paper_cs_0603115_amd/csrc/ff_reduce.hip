@@ -356,7 +356,9 @@ __device__ __forceinline__ void add_group(const typename Terms<In>::G &q, float2
     }
 }
 
-// The persistent partials launch.  Chunk c goes to workgroup c mod gridDim.x.
+// The persistent partials launch.  Each wavefront is an independent worker:
+// global wavefront w reduces chunks w, w + W, w + 2W, ... (W wavefronts in
+// the grid) to a partial with a butterfly, no barriers.
 // VEC (all planes 16-byte aligned): the float4 groups lying wholly inside
 // the chunk are read UNROLL at a time per lane, all loads issued before any
 // arithmetic; the at most 3 + 3 elements before the first and after the
@@ -366,15 +368,14 @@ template <class In, class Acc, int BLOCK, int UNROLL, bool VEC>
 __global__ __launch_bounds__(BLOCK) void dot_partials(In in, Workspace w, int32_t nvec)
 {
     constexpr int kWaves = BLOCK / 64;
-    __shared__ float2 wave_part[kWaves];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = static_cast<int64_t>(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+    const int64_t nw = static_cast<int64_t>(gridDim.x) * kWaves;
     int64_t nchunks = w.chunk_start[nvec];
     if (nchunks > w.cap)
         nchunks = w.cap;
 
-    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    for (int64_t c = gw; c < nchunks; c += nw) {
         const longlong2 r = w.ranges[c];
         const int64_t s = r.x, e = r.y;
 
@@ -387,36 +388,35 @@ __global__ __launch_bounds__(BLOCK) void dot_partials(In in, Workspace w, int32_
             int64_t gb = e >> 2;               // end of the whole groups
             if (gb < ga)
                 gb = ga;                       // s and e inside one group
-            const int64_t gstep = static_cast<int64_t>(BLOCK) * UNROLL;
-            int64_t g = ga + tid;
-            for (; g + (UNROLL - 1) * BLOCK < gb; g += gstep) {
+            int64_t g = ga + lane;
+            for (; g + (UNROLL - 1) * 64 < gb; g += 64 * UNROLL) {
                 typename Terms<In>::G q[UNROLL];
 #pragma unroll
                 for (int u = 0; u < UNROLL; ++u)
-                    q[u] = Terms<In>::load(in, g + u * BLOCK);
+                    q[u] = Terms<In>::load(in, g + u * 64);
 #pragma unroll
                 for (int u = 0; u < UNROLL; ++u)
                     add_group<In, Acc>(q[u], acc);
             }
-            for (; g < gb; g += BLOCK)
+            for (; g < gb; g += 64)
                 add_group<In, Acc>(Terms<In>::load(in, g), acc);
-            // head [s, 4 ga) and tail [4 gb, e) elements, by threads 0..2
-            // and 64..66 (when a chunk lies inside one group, gb = ga and
-            // the head covers it)
+            // head [s, 4 ga) and tail [4 gb, e) elements, by lanes 0..2 and
+            // 32..34 (when a chunk lies inside one group, gb = ga and the
+            // head covers it)
             const int64_t head_end = 4 * ga < e ? 4 * ga : e;
             const int64_t tail_beg = 4 * gb > s ? 4 * gb : s;
             int64_t i = -1;
-            if (tid < 3 && s + tid < head_end)
-                i = s + tid;
-            else if (tid >= 64 && tid < 67 && tail_beg + (tid - 64) < e && tail_beg >= head_end)
-                i = tail_beg + (tid - 64);
+            if (lane < 3 && s + lane < head_end)
+                i = s + lane;
+            else if (lane >= 32 && lane < 35 && tail_beg + (lane - 32) < e)
+                i = tail_beg + (lane - 32);
             if (i >= 0) {
                 float ph, pl;
                 Terms<In>::one(in, i, ph, pl);
                 Acc::add(acc[0].x, acc[0].y, ph, pl);
             }
         } else {
-            for (int64_t i = s + tid; i < e; i += BLOCK) {
+            for (int64_t i = s + lane; i < e; i += 64) {
                 float ph, pl;
                 Terms<In>::one(in, i, ph, pl);
                 Acc::add(acc[0].x, acc[0].y, ph, pl);
@@ -429,16 +429,7 @@ __global__ __launch_bounds__(BLOCK) void dot_partials(In in, Workspace w, int32_
         Acc::merge(h, l, h2, l2);
         wave_allreduce<Acc>(h, l);
         if (lane == 0)
-            wave_part[wave] = make_float2(h, l);
-        __syncthreads();
-        if (tid == 0) {
-            float th = wave_part[0].x, tl = wave_part[0].y;
-#pragma unroll
-            for (int k = 1; k < kWaves; ++k)
-                Acc::merge(th, tl, wave_part[k].x, wave_part[k].y);
-            w.partials[c] = make_float2(th, tl);
-        }
-        __syncthreads();
+            w.partials[c] = make_float2(h, l);
     }
 }
 
@@ -453,7 +444,7 @@ ff_status resolve_cfg(const ff_dot_cfg *cfg, Cfg &out)
     out.block = 512;
     out.chunk = 16384;
     out.grid = 0;
-    out.unroll = 2;
+    out.unroll = 8;
     if (cfg) {
         if (cfg->block)
             out.block = cfg->block;
@@ -480,7 +471,7 @@ int default_grid()
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    return 2 * (cus > 0 ? cus : 256);
+    return 8 * (cus > 0 ? cus : 256);
 }
 
 template <class In, class Acc, int BLOCK, int UNROLL>
@@ -666,7 +657,7 @@ ff_status ff_dot_batched_autotune(const float *x, const float *y, const int64_t 
         return ffh::hip_failure(hipGetLastError());
     static const int kBlocks[] = {256, 512};
     static const int kUnrolls[] = {1, 2, 4, 8};
-    static const int kChunks[] = {4096, 8192, 16384, 32768, 65536};
+    static const int kChunks[] = {1024, 2048, 4096, 8192, 16384, 32768};
     static const int kPerCu[] = {2, 4, 8, 16};
     hipStream_t st = ffh::as_stream(stream);
     hipEvent_t e0, e1;

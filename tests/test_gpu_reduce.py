@@ -37,12 +37,15 @@ def _announce(msg):
 
 
 def tree_depth(lengths, cfg):
-    block, chunk, _, _ = cfg
-    block = block or 256
+    """Longest chain of Add22s behind a result: a lane's accumulator over its
+    share of a chunk (one wavefront per chunk, 4 accumulators per lane, plus
+    one edge element), 2 merges, the 6-level butterfly, then the chunk
+    partials lane-strided, a second butterfly, and slack."""
+    _, chunk, _, _ = cfg
     chunk = chunk or 16384
-    per_lane = math.ceil(chunk / (4 * block)) if chunk >= 4 else 1
+    per_lane = math.ceil(chunk / (4 * 64)) + 1
     nch = max(1, max(math.ceil(int(n) / chunk) for n in lengths))
-    return per_lane + 2 + 6 + (block // 64 - 1) + math.ceil(nch / 64) + 6 + 2
+    return per_lane + 2 + 6 + math.ceil(nch / 64) + 6 + 2
 
 
 def check_against_exact(x, y, offs, got, cfg, label, target=TWO_M44):
