@@ -18,8 +18,9 @@
 // pair is an integer GEMM on matrix cores:
 //   * int8 digits, v_mfma_i32_32x32x32_i8, int32 accumulation;
 //   * BF16 digits (integers |d| <= 128 are exact in BF16),
-//     v_mfma_f32_32x32x16_bf16, FP32 accumulation moved into int32
-//     accumulators every 128 k, before any partial sum can exceed 2^24.
+//     v_mfma_f32_32x32x16_bf16, FP32 accumulation folded every 128 k,
+//     before any partial sum can exceed 2^24, into one exact 96-bit integer
+//     per output, T += sum_D S_D 256^(6-D).
 // All partial sums are exact integers, so the hardware's accumulation order
 // does not matter.  Pairs on the same anti-diagonal D = t + u share one
 // accumulator (same weight): |S_D| <= 7 K 2^14 < 2^31 for K <= 16384 (longer
@@ -522,19 +523,40 @@ __device__ __forceinline__ void store_block(const Acc (&acc)[kS], const i32x16 (
     }
 }
 
-// Launch shape of the sliced product: WM x WN wavefronts (256 or 512
-// threads), each owning a 32 x 32 block of C as S diagonal accumulators, and
-// a ring of 3 K-stages in LDS (two in flight while one is consumed).
-template <class Dg> struct SlicedShape;
-// int8: 8 wavefronts (2 per SIMD, <= 256 registers each), 128 x 64 outputs,
-// 3 x 42 KiB stages.
-template <> struct SlicedShape<DigitsI8> {
-    static constexpr int WM = 4, WN = 2, WAVES_PER_SIMD = 2;
-};
-// BF16: FP32 and int32 diagonal accumulators need ~400 registers, so one
-// wavefront per SIMD: 4 wavefronts, 64 x 64 outputs, 3 x 28 KiB stages.
-template <> struct SlicedShape<DigitsBF16> {
-    static constexpr int WM = 2, WN = 2, WAVES_PER_SIMD = 1;
+// As store_block, with T already formed (96-bit two's complement words).
+template <int WM, int WN>
+__device__ __forceinline__ void store_block_t96(const uint32_t (&t96)[16][3], int64_t M,
+                                                int64_t N, int bi, int bj, int wm, int wn,
+                                                int lane, const uint32_t *__restrict__ rowmax,
+                                                const uint32_t *__restrict__ colmax,
+                                                float *__restrict__ Ch, float *__restrict__ Cl,
+                                                int64_t ldc, int accumulate)
+{
+    const int64_t j = static_cast<int64_t>(bj) * (32 * WN) + wn * 32 + (lane & 31);
+    const int fj = j < N ? exponent_bound(colmax[j]) : 0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t i = static_cast<int64_t>(bi) * (32 * WM) + wm * 32 + m;
+        if (i >= M || j >= N)
+            continue;
+        __int128 T = static_cast<__int128>(static_cast<int32_t>(t96[r][2]));
+        T = (T << 64) | (static_cast<__int128>(t96[r][1]) << 32) |
+            static_cast<__int128>(t96[r][0]);
+        float h, l;
+        i128_to_ff(T, exponent_bound(rowmax[i]) + fj + kEpiShift, h, l);
+        if (accumulate)
+            ffd::add22(Ch[i * ldc + j], Cl[i * ldc + j], h, l, h, l);
+        Ch[i * ldc + j] = h;
+        Cl[i * ldc + j] = l;
+    }
+}
+
+// Launch shape of the sliced product: WM x WN = 4 x 2 wavefronts (2 per
+// SIMD), each owning a 32 x 32 block of C as S diagonal accumulators, for a
+// 128 x 64 block per workgroup; a ring of 3 K-stages of 42 KiB in LDS.
+template <class Dg> struct SlicedShape {
+    static constexpr int WM = 4, WN = 2;
 };
 
 // s_waitcnt immediate that waits until at most n vector-memory operations of
@@ -546,182 +568,12 @@ constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) |
 // "memory" clobber keeps the compiler from moving LDS accesses across.
 __device__ __forceinline__ void barrier_no_fence() { asm volatile("s_barrier" ::: "memory"); }
 
-// The sliced product for one output block of (32 WM) x (32 WN).  Each K-stage
-// is the block's digit tiles (A and B, all S slices, 2 KiB per 64-row tile)
-// copied from memory straight into LDS with 16-byte global_load_lds (no
-// staging registers).  Three LDS slots form a ring: while the MFMAs of stage
-// k run, stages k + 1 (landed or landing) and k + 2 (issued at the start of
-// stage k) are in flight, so a DMA has two stages' time to arrive.
-template <class Dg, int WM, int WN, int WPS>
-__global__ __launch_bounds__(64 * WM * WN, WPS) void gemm_sliced(
-    int64_t M, int64_t N, int nBI, int nBJ, int nBK, int bk0, int bk1,
-    const uint8_t *__restrict__ Ap, const uint8_t *__restrict__ Bp,
-    const uint32_t *__restrict__ rowmax, const uint32_t *__restrict__ colmax,
-    float *__restrict__ Ch, float *__restrict__ Cl, int64_t ldc, int accumulate)
-{
-    using Acc = typename AccOf<Dg>::T;
-    constexpr int kWaves = WM * WN;
-    constexpr int kTA = WM / 2, kTB = WN / 2;             // 64-row tiles per slice
-    constexpr int kSlotBytes = kS * (kTA + kTB) * kTileBytes;
-    constexpr int kHalves = 2 * kS * (kTA + kTB);         // 1 KiB wavefront loads per stage
-    constexpr int kQ = kHalves / kWaves, kR = kHalves % kWaves;
-    uint8_t *const slot0 = lds_slot<kSlotBytes, 0>();
-    uint8_t *const slot1 = lds_slot<kSlotBytes, 1>();
-    uint8_t *const slot2 = lds_slot<kSlotBytes, 2>();
-
-    const int bj = blockIdx.x, bi = blockIdx.y;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave / WN, wn = wave % WN;
-    const int64_t a_slice = static_cast<int64_t>(nBI) * nBK * kTileBytes;
-    const int64_t b_slice = static_cast<int64_t>(nBJ) * nBK * kTileBytes;
-
-    Acc acc[kS];
-    i32x16 iacc[kS];
-#pragma unroll
-    for (int d = 0; d < kS; ++d) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            acc[d][r] = 0;
-            iacc[d][r] = 0;
-        }
-    }
-
-    // Half-tile h of a stage: A halves first (slice-major, tile, half),
-    // then B halves.  Wavefront w loads halves w, w + kWaves, ... (kQ or
-    // kQ + 1 instructions).
-    auto fetch = [&](int bk, uint8_t *slot) {
-#pragma unroll
-        for (int j = 0; j < kQ + (kR ? 1 : 0); ++j) {
-            const int h = wave + j * kWaves;
-            if (h < kHalves) {
-                const int tile = h >> 1, half = h & 1;
-                const uint8_t *src;
-                if (tile < kS * kTA) {
-                    const int t = tile / kTA, tt = tile % kTA;
-                    src = Ap + t * a_slice + tile_base(0, bi * kTA + tt, bk, nBI, nBK);
-                } else {
-                    const int tb = tile - kS * kTA;
-                    const int t = tb / kTB, tt = tb % kTB;
-                    src = Bp + t * b_slice + tile_base(0, bj * kTB + tt, bk, nBJ, nBK);
-                }
-                src += half * 1024 + lane * 16;
-                uint8_t *dst = slot + tile * kTileBytes + half * 1024;
-                // address-space conversions (generic -> global / LDS) need C casts
-                __builtin_amdgcn_global_load_lds((global_void_ptr)(const void *)src,
-                                                 (lds_void_ptr)(void *)dst, 16, 0, 0);
-            }
-        }
-    };
-
-    // Wait until only the newest stage's DMA (issued last, when `newest`)
-    // may be outstanding: a wavefront issues kQ + 1 instructions per stage
-    // if wave < kR, else kQ, and vmcnt counts them in issue order.
-    auto wait_older_stages = [&](bool newest) {
-        if (!newest)
-            __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
-        else if (kR != 0 && wave < kR)
-            __builtin_amdgcn_s_waitcnt(vmcnt_imm(kQ + 1));
-        else
-            __builtin_amdgcn_s_waitcnt(vmcnt_imm(kQ));
-    };
-
-    // Operand rows of this lane: A row wm*32 + lane%32 lives in A tile
-    // (wm / 2) at row 32*(wm % 2) + lane%32; likewise B.
-    const int ta = wm >> 1, rla = 32 * (wm & 1) + (lane & 31);
-    const int tb = wn >> 1, rlb = 32 * (wn & 1) + (lane & 31);
-    const int oa = ta * kTileBytes + tile_swizzle(rla, lane >> 5);
-    const int ob = kS * kTA * kTileBytes + tb * kTileBytes + tile_swizzle(rlb, lane >> 5);
-
-    // One K-stage, reading `slot` (stage bk, landed) and filling `dma_slot`
-    // with stage bk + 2 (its previous content, stage bk - 1, was read by
-    // every wavefront before the last barrier).  Fragments are read in the
-    // order the MFMAs use them (fb[0], fa[0..6], fb[1..6]), so that the
-    // first MFMA needs only the first two reads.  The stage ends once this wavefront's share of stage bk + 1 has
-    // landed (only stage bk + 2 may still be in flight) and every wavefront
-    // has arrived.
-    auto stage = [&](const uint8_t *slot, uint8_t *dma_slot, int bk) {
-        const bool more = bk + 2 < bk1;
-        uint4 fa[kS], fb[kS];
-        fb[0] = *reinterpret_cast<const uint4 *>(slot + ob);
-#pragma unroll
-        for (int t = 0; t < kS; ++t)
-            fa[t] = *reinterpret_cast<const uint4 *>(slot + t * kTA * kTileBytes + oa);
-#pragma unroll
-        for (int u = 1; u < kS; ++u)
-            fb[u] = *reinterpret_cast<const uint4 *>(slot + u * kTB * kTileBytes + ob);
-        // the DMA goes out after the reads: a conservative wait the compiler
-        // may place before the reads then never covers this stage's DMA.
-        // (Scheduling fences only for int8: the BF16 kernel's ~450 live
-        // registers leave the scheduler no room for them.)
-        if constexpr (Dg::kExtractStages == 0)
-            __builtin_amdgcn_sched_barrier(0);
-        if (more)
-            fetch(bk + 2, dma_slot);
-        if constexpr (Dg::kExtractStages == 0)
-            __builtin_amdgcn_sched_barrier(0);
-        // digit pairs (t, u), t + u <= S - 1, row by row; consecutive
-        // instructions feed different diagonal accumulators
-#pragma unroll
-        for (int u = 0; u < kS; ++u) {
-#pragma unroll
-            for (int t = 0; t + u < kS; ++t)
-                acc[t + u] = mma(fa[t], fb[u], acc[t + u], Dg{});
-            if constexpr (Dg::kExtractStages == 0)
-                __builtin_amdgcn_sched_barrier(0);
-        }
-        if constexpr (Dg::kExtractStages > 0) {
-            if ((bk - bk0 + 1) % Dg::kExtractStages == 0 || bk + 1 == bk1) {
-#pragma unroll
-                for (int d = 0; d < kS; ++d)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        iacc[d][r] += static_cast<int>(acc[d][r]);
-                        acc[d][r] = 0.0f;
-                    }
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        wait_older_stages(more);
-        barrier_no_fence();
-    };
-
-    if (bk0 < bk1)
-        fetch(bk0, slot0);
-    if (bk0 + 1 < bk1)
-        fetch(bk0 + 1, slot1);
-    wait_older_stages(bk0 + 1 < bk1);
-    barrier_no_fence();
-    // (The two loop forms are equivalent; each is the one the register
-    // allocator handles without spilling for its digit type.)
-    if constexpr (Dg::kExtractStages == 0) {
-        for (int bk = bk0; bk < bk1; bk += 3) {
-            stage(slot0, slot2, bk);
-            if (bk + 1 < bk1)
-                stage(slot1, slot0, bk + 1);
-            if (bk + 2 < bk1)
-                stage(slot2, slot1, bk + 2);
-        }
-    } else {
-        for (int bk = bk0; bk < bk1; bk += 3) {
-            stage(slot0, slot2, bk);
-            if (bk + 1 >= bk1)
-                break;
-            stage(slot1, slot0, bk + 1);
-            if (bk + 2 >= bk1)
-                break;
-            stage(slot2, slot1, bk + 2);
-        }
-    }
-
-    store_block<Dg, WM, WN>(acc, iacc, M, N, bi, bj, wm, wn, lane, rowmax, colmax, Ch, Cl, ldc,
-                            accumulate);
-}
-
 // s_waitcnt immediate that waits until at most n LDS operations of this
 // wavefront are outstanding.
 constexpr int lgkmcnt_imm(int n) { return 15 | (3 << 14) | (7 << 4) | ((n & 15) << 8); }
 
-// The int8 product with a ping-pong schedule.  The 8 wavefronts form two
+// The sliced product with a ping-pong schedule (int8 digits, and BF16 digits
+// with exact 96-bit per-output drains).  The 8 wavefronts form two
 // groups (waves 0-3 and 4-7: one of each on every SIMD) that run half a
 // K-stage apart: while one group reads a stage's fragments from LDS, the
 // other runs the MFMAs of the fragments it read before, so the LDS reads
@@ -736,14 +588,15 @@ constexpr int lgkmcnt_imm(int n) { return 15 | (3 << 14) | (7 << 4) | ((n & 15) 
 // waits for its reads to land before that barrier).  A wavefront waits for
 // its previous DMA share at the start of its next read phase, one stage
 // after issuing it, and so before the barrier that precedes any read of it.
-template <int WM, int WN>
+template <class Dg, int WM, int WN>
 __global__ __launch_bounds__(64 * WM * WN, 2) void gemm_sliced_pp(
     int64_t M, int64_t N, int nBI, int nBJ, int nBK, int bk0, int bk1,
     const uint8_t *__restrict__ Ap, const uint8_t *__restrict__ Bp,
     const uint32_t *__restrict__ rowmax, const uint32_t *__restrict__ colmax,
     float *__restrict__ Ch, float *__restrict__ Cl, int64_t ldc, int accumulate)
 {
-    using Dg = DigitsI8;
+    using Acc = typename AccOf<Dg>::T;
+    constexpr bool kDrain = Dg::kExtractStages > 0;
     constexpr int kWaves = WM * WN;
     static_assert(kWaves == 8, "two groups of four wavefronts");
     constexpr int kTA = WM / 2, kTB = WN / 2;
@@ -762,12 +615,46 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void gemm_sliced_pp(
     const int64_t a_slice = static_cast<int64_t>(nBI) * nBK * kTileBytes;
     const int64_t b_slice = static_cast<int64_t>(nBJ) * nBK * kTileBytes;
 
-    i32x16 acc[kS];
+    Acc acc[kS];
 #pragma unroll
     for (int d = 0; d < kS; ++d)
 #pragma unroll
         for (int r = 0; r < 16; ++r)
             acc[d][r] = 0;
+    // BF16 digits: the FP32 stage sums are exact only up to 2^24, so every
+    // kExtractStages stages they are folded into one exact integer per
+    // output, T += sum_D S_D 256^(S-1-D), kept as 96 bits (three words,
+    // two's complement): |T| < 7 K 2^14 2^49 < 2^78 for K <= 16384.
+    uint32_t t96[kDrain ? 16 : 1][3];
+#pragma unroll
+    for (int r = 0; r < (kDrain ? 16 : 1); ++r)
+        t96[r][0] = t96[r][1] = t96[r][2] = 0u;
+    auto drain = [&]() {
+        if constexpr (kDrain) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                __int128 t = 0;
+#pragma unroll
+                for (int d = 0; d < kS; ++d)
+                    t = (t << 8) + static_cast<__int128>(static_cast<int>(acc[d][r]));
+                __int128 T = static_cast<__int128>(static_cast<int32_t>(t96[r][2]));
+                T = (T << 64) | (static_cast<__int128>(t96[r][1]) << 32) |
+                    static_cast<__int128>(t96[r][0]);
+                T += t;
+                t96[r][0] = static_cast<uint32_t>(T);
+                t96[r][1] = static_cast<uint32_t>(T >> 32);
+                t96[r][2] = static_cast<uint32_t>(T >> 64);
+            }
+#pragma unroll
+            for (int d = 0; d < kS; ++d)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    acc[d][r] = 0.0f;
+        }
+    };
+    auto drain_due = [&](int bk) {
+        return kDrain && ((bk - bk0 + 1) % (kDrain ? Dg::kExtractStages : 1) == 0 || bk + 1 == bk1);
+    };
 
     auto fetch = [&](int bk, uint8_t *slot) {
 #pragma unroll
@@ -848,6 +735,8 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void gemm_sliced_pp(
             read_phase(slot, dma_slot, bk);
             barrier_no_fence();
             mfmas();
+            if (drain_due(bk))
+                drain();
             __builtin_amdgcn_sched_barrier(0);
             barrier_no_fence();
         };
@@ -860,8 +749,11 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void gemm_sliced_pp(
         }
     } else {
         auto stage1 = [&](const uint8_t *slot, uint8_t *dma_slot, int bk) {
-            if (bk > bk0)
+            if (bk > bk0) {
                 mfmas();
+                if (drain_due(bk - 1))
+                    drain();
+            }
             __builtin_amdgcn_sched_barrier(0);
             barrier_no_fence();
             read_phase(slot, dma_slot, bk);
@@ -877,12 +769,18 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void gemm_sliced_pp(
             if (bk + 2 < bk1)
                 stage1(slot2, slot1, bk + 2);
         }
-        if (bk0 < bk1)
+        if (bk0 < bk1) {
             mfmas();   // the last stage
+            drain();   // (always due after the last stage)
+        }
     }
     __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
-    store_block<Dg, WM, WN>(acc, acc, M, N, bi, bj, wm, wn, lane, rowmax, colmax, Ch, Cl, ldc,
-                            accumulate);
+    if constexpr (kDrain)
+        store_block_t96<WM, WN>(t96, M, N, bi, bj, wm, wn, lane, rowmax, colmax, Ch, Cl, ldc,
+                                accumulate);
+    else
+        store_block<Dg, WM, WN>(acc, acc, M, N, bi, bj, wm, wn, lane, rowmax, colmax, Ch, Cl,
+                                ldc, accumulate);
 }
 
 struct SliceGeom {
@@ -963,14 +861,9 @@ ff_status sliced_gemm(int64_t M, int64_t N, int64_t K, const float *Ah, const fl
     int bk0 = 0;
     do {
         const int bk1 = (bk0 + stages_per_chunk < g.nBK) ? bk0 + stages_per_chunk : g.nBK;
-        if constexpr (Dg::kExtractStages == 0)
-            hipLaunchKernelGGL((gemm_sliced_pp<Sh::WM, Sh::WN>), grid, dim3(64 * Sh::WM * Sh::WN),
-                               0, st, M, N, g.nBI, g.nBJ, g.nBK, bk0, bk1, Ap, Bp, rowmax, colmax,
-                               Ch, Cl, ldc, bk0 > 0 ? 1 : 0);
-        else
-            hipLaunchKernelGGL((gemm_sliced<Dg, Sh::WM, Sh::WN, Sh::WAVES_PER_SIMD>), grid,
-                               dim3(64 * Sh::WM * Sh::WN), 0, st, M, N, g.nBI, g.nBJ, g.nBK, bk0,
-                               bk1, Ap, Bp, rowmax, colmax, Ch, Cl, ldc, bk0 > 0 ? 1 : 0);
+        hipLaunchKernelGGL((gemm_sliced_pp<Dg, Sh::WM, Sh::WN>), grid, dim3(64 * Sh::WM * Sh::WN),
+                           0, st, M, N, g.nBI, g.nBJ, g.nBK, bk0, bk1, Ap, Bp, rowmax, colmax, Ch,
+                           Cl, ldc, bk0 > 0 ? 1 : 0);
         bk0 = bk1;
     } while (bk0 < g.nBK);
     return ffh::launch_status();
