@@ -694,13 +694,22 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void gemm_sliced_pp(
         for (int u = 1; u < kS; ++u)
             fb[u] = *reinterpret_cast<const uint4 *>(slot + u * kTB * kTileBytes + ob);
     };
+    // The 28 digit pairs (t, u) in an order that keeps the updates of each
+    // diagonal accumulator t + u at least three instructions apart, so that
+    // no MFMA waits for the one before it (in a phase the SIMD's other
+    // wavefront issues no MFMAs that could fill such a gap).
     auto mfmas = [&]() {
+        constexpr int kOrder[28][2] = {
+            {0, 6}, {0, 5}, {0, 4}, {0, 3}, {1, 5}, {1, 4}, {1, 3}, {1, 2}, {2, 4}, {2, 3},
+            {2, 2}, {2, 1}, {3, 3}, {3, 2}, {3, 1}, {3, 0}, {4, 2}, {4, 1}, {4, 0}, {0, 2},
+            {5, 1}, {5, 0}, {1, 1}, {0, 1}, {6, 0}, {2, 0}, {1, 0}, {0, 0}};
+        static_assert(kS == 7, "the order lists the 28 pairs of 7 digits");
 #pragma unroll
-        for (int u = 0; u < kS; ++u) {
-#pragma unroll
-            for (int t = 0; t + u < kS; ++t)
-                acc[t + u] = mma(fa[t], fb[u], acc[t + u], Dg{});
-            __builtin_amdgcn_sched_barrier(0);
+        for (int q = 0; q < 28; ++q) {
+            const int t = kOrder[q][0], u = kOrder[q][1];
+            acc[t + u] = mma(fa[t], fb[u], acc[t + u], Dg{});
+            if ((q & 3) == 3)
+                __builtin_amdgcn_sched_barrier(0);
         }
     };
     // A read phase: this wavefront's previous DMA share (stage bk + 1) has
