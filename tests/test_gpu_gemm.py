@@ -179,3 +179,31 @@ def test_full_size_4096():
     assert same_bits(Cpn[0], Ch) and same_bits(Cpn[1], Cl)
     del A, B, C8, C16, Cp
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("algo", ALGOS + ["fma"])
+def test_strided_operands_and_output(algo):
+    # leading dimensions larger than the rows (views into wider buffers),
+    # one of them not a multiple of 4 and one operand starting 4 bytes past
+    # 16-byte alignment: the slicing kernels take their element paths
+    ff = _ff()
+    M, N, K = 70, 45, 133
+    baseA = fi.gaussian_ff((M, K + 5), 71).cuda()
+    baseB = fi.gaussian_ff((K, N + 9), 72).cuda()
+    A = baseA[:, :, :K]                       # lda = K + 5
+    B = baseB[:, :, 1:N + 1]                  # ldb = N + 9, base + 4 bytes
+    Cbuf = torch.full((2, M, N + 3), 7.0, device="cuda")
+    C = Cbuf[:, :, :N]                        # ldc = N + 3
+    ff.ff_gemm(A, B, algo=_algo(algo), out=C)
+    torch.cuda.synchronize()
+    assert torch.all(Cbuf[:, :, N:] == 7.0)   # padding columns untouched
+    Ac, Bc = A.contiguous(), B.contiguous()
+    if algo == "fma":
+        Cn = C.cpu().numpy()
+        Ch, Cl = oracle.gemm_ff_seq(Ac[0].cpu().numpy(), Ac[1].cpu().numpy(),
+                                    Bc[0].cpu().numpy(), Bc[1].cpu().numpy())
+        assert same_bits(Cn[0], Ch) and same_bits(Cn[1], Cl)
+    else:
+        check_entries(Ac, Bc, C.contiguous(), range(M), range(N), f"{algo} strided")
+        Cref = ff.ff_gemm(Ac, Bc, algo=_algo(algo))
+        assert torch.equal(Cref.view(torch.int32), C.contiguous().view(torch.int32))

@@ -215,3 +215,22 @@ def test_autotuner_returns_a_valid_fast_shape(tmp_path, monkeypatch):
     assert autotune.dot_cfg(x, y, offs, search=False) == cfg      # served from the file
     got = _ff().ff_dot_batched(x, y, offs, cfg=cfg)
     check_against_exact(x, y, offs, got, cfg, "tuned")
+
+
+def test_out_of_range_offsets_are_clamped():
+    # offsets outside [0, total] are clamped on the device (no access outside
+    # the arrays): vector 0 = [0, total), vector 1 = [total, total) empty,
+    # vector 2 = [0, 10)
+    ff = _ff()
+    x, y, _ = fi.batched_dot(61, nvec=2, log2_max=12)
+    total = x.numel()
+    offs = torch.tensor([0, total + 100, -5, 10], dtype=torch.int64)
+    got = ff.ff_dot_batched(x.cuda(), y.cuda(), offs.cuda()).cpu().numpy()
+    xn, yn = x.numpy(), y.numpy()
+    ex0 = oracle.exact_dot(xn, yn)
+    ab0 = oracle.exact_dot(np.abs(xn), np.abs(yn))
+    assert abs(frac(got[0, 0]) + frac(got[1, 0]) - ex0) <= TWO_M44 * ab0
+    assert got[0, 1] == 0 and got[1, 1] == 0
+    ex2 = oracle.exact_dot(xn[:10], yn[:10])
+    assert abs(frac(got[0, 2]) + frac(got[1, 2]) - ex2) <= TWO_M44 * oracle.exact_dot(
+        np.abs(xn[:10]), np.abs(yn[:10]))
