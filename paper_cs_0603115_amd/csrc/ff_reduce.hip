@@ -5,8 +5,9 @@
 // into chunks of `chunk` elements.  Four stream-ordered launches:
 //   plan      one workgroup: chunk counts per vector and their exclusive scan
 //   records   one wavefront per vector: the element range of each chunk
-//   partials  persistent: chunk c is reduced by workgroup c mod grid into a
-//             float-float partial
+//   partials  persistent: each wavefront of the grid is a worker, and chunk
+//             c is reduced by worker c mod (grid * waves per workgroup) into
+//             a float-float partial
 //   combine   one wavefront per vector: Add22 of the vector's partials
 // Launch boundaries order the phases, so no fences or atomics are needed: a
 // device-scope fence on gfx950 writes back and invalidates the L2 of the
