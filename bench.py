@@ -113,6 +113,33 @@ def secondary(stream) -> dict:
     dev = torch.device("cuda:0")
     out = {}
 
+    n = 1 << 20
+    log("[bench] ff_add / ff_mul on 2^20 base pairs, cache-warm and after a cache flush")
+    a = fi.base_ff(n, 115001, device=dev)
+    b = fi.base_ff(n, 115011, device=dev)
+    r = ff.ff_empty((n,), device=dev)
+    # 1 GiB written between launches evicts the 25 MB working set from L2 and
+    # the 256 MB Infinity Cache; only the operator's own launch is timed
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    small = {}
+    for name, fn in (("add", ff.ff_add), ("mul", ff.ff_mul)):
+        warm_ms = _time_launches(lambda: fn(a, b, out=r, stream=stream), 200, stream)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(20)]
+        for s_ev, e_ev in evs:
+            flush.zero_()
+            s_ev.record(stream)
+            fn(a, b, out=r, stream=stream)
+            e_ev.record(stream)
+        torch.cuda.synchronize()
+        cold_ms = sum(s_ev.elapsed_time(e_ev) for s_ev, e_ev in evs) / len(evs)
+        small[name] = {"warm_us": round(warm_ms * 1e3, 2), "warm_ff_ops/s": n / (warm_ms * 1e-3),
+                       "flushed_us": round(cold_ms * 1e3, 2),
+                       "flushed_ff_ops/s": n / (cold_ms * 1e-3)}
+    out["elementwise_2p20"] = small
+    del a, b, r, flush
+    torch.cuda.empty_cache()
+
     log("[bench] batched dot: 4096 vectors, lengths floor(2^U[6,20])")
     x, y, offs = fi.batched_dot(115003, device=dev)
     total = x.numel()

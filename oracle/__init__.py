@@ -36,7 +36,8 @@ CFLAGS = [
 ]
 
 ELEMENTWISE_OPS = {"add": 0, "sub": 1, "mul": 2, "mul_dekker": 3, "div": 4,
-                   "add_accurate": 5, "sub_accurate": 6}
+                   "add_accurate": 5, "sub_accurate": 6, "mul_accurate": 7,
+                   "div_accurate": 8}
 
 
 def build(force: bool = True, cc: str = "gcc", src: str = _SRC, out: str = _SO) -> str:
@@ -69,6 +70,8 @@ _SIGS = {
     "oracle_div22": ([_F, _F, _F, _F, _F, _F, _i64, _int], None),
     "oracle_add22_accurate": ([_F, _F, _F, _F, _F, _F, _i64], None),
     "oracle_sub22_accurate": ([_F, _F, _F, _F, _F, _F, _i64], None),
+    "oracle_mul22_accurate": ([_F, _F, _F, _F, _F, _F, _i64], None),
+    "oracle_div22_accurate": ([_F, _F, _F, _F, _F, _F, _i64], None),
     "oracle_elementwise": ([_int, _F, _F, _F, _F, _F, _F, _i64], _int),
     "oracle_dot_seq": ([_F, _F, _i64, _F], None),
     "oracle_dot_ff_seq": ([_F, _F, _i64, _F, _F, _i64, _i64, _F], None),
@@ -212,6 +215,18 @@ def sub22_accurate(ah, al, bh, bl):
     return _binary("oracle_sub22_accurate", ah, al, bh, bl)
 
 
+def mul22_accurate(ah, al, bh, bl):
+    """FMA-based float-float product (DWTimesDW3 of Joldes, Muller and
+    Popescu, 2017): relative error at most 5u^2, u = 2^-24."""
+    return _binary("oracle_mul22_accurate", ah, al, bh, bl)
+
+
+def div22_accurate(ah, al, bh, bl):
+    """Reciprocal-based float-float quotient (DWDivDW3 of Joldes, Muller and
+    Popescu, 2017): relative error at most 9.8u^2, u = 2^-24."""
+    return _binary("oracle_div22_accurate", ah, al, bh, bl)
+
+
 def mul22(ah, al, bh, bl, dekker: bool = False):
     """Mul22 theorem (section 4.1), final step Add12(t1, t3)."""
     return _binary("oracle_mul22", ah, al, bh, bl, int(dekker))
@@ -285,7 +300,8 @@ def f32_ref(op: str, a, b, c=None):
     return r
 
 
-FF_ERROR_OPS = {"add22": 0, "mul22": 1, "add12": 2, "mul12": 3}
+FF_ERROR_OPS = {"add22": 0, "mul22": 1, "add12": 2, "mul12": 3, "div22": 4,
+                "mul22_accurate": 5, "div22_accurate": 6}
 
 
 def ff_errors(op: str, ah, al, bh, bl, rh, rl):

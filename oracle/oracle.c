@@ -163,6 +163,60 @@ static void add22_accurate(float ah, float al, float bh, float bl, float *rh,
     fast_add12(vh, w, rh, rl);
 }
 
+/* FMA-based float-float product (not in the paper; a tighter-bound
+ * alternative to Mul22): the "DWTimesDW3" algorithm of Joldes, Muller and
+ * Popescu (ACM TOMS 2017, Algorithm 12), relative error at most 5u^2,
+ * u = 2^-24:
+ *   (ch, cl1) = TwoProd(ah, bh);  tl0 = al * bl;  tl1 = fma(ah, bl, tl0);
+ *   cl2 = fma(al, bh, tl1);  cl3 = cl1 + cl2;  (rh, rl) = Fast2Sum(ch, cl3).
+ * Fast2Sum is exact here: |cl3| is below ulp(ch) for normalised inputs. */
+static void mul22_accurate(float ah, float al, float bh, float bl, float *rh,
+                           float *rl)
+{
+    float ch, cl1;
+    mul12_fma(ah, bh, &ch, &cl1);
+    float tl0 = al * bl;
+    float tl1 = fmaf(ah, bl, tl0);
+    float cl2 = fmaf(al, bh, tl1);
+    float cl3 = cl1 + cl2;
+    fast_add12(ch, cl3, rh, rl);
+}
+
+/* Reciprocal-based float-float division (not in the paper): the "DWDivDW3"
+ * algorithm of Joldes, Muller and Popescu (ACM TOMS 2017, Algorithm 18),
+ * relative error at most 9.8u^2.  One Newton step refines th = 1/bh into a
+ * float-float reciprocal m of b, and the quotient is the product a * m:
+ *   th = 1 / bh;  rh = fma(-bh, th, 1) (exact);  rl = -bl * th;
+ *   (eh, el) = TwoSum(rh, rl);
+ *   (dh, dl) = (eh, el) * th         [DWTimesFP3: TwoProd(eh, th),
+ *                                      fma(el, th, error), Fast2Sum];
+ *   (mh, ml) = (dh, dl) + th         [DWPlusFP: TwoSum(dh, th), add the
+ *                                      low words, Fast2Sum];
+ *   (rh, rl) = a * m                 [DWTimesDW3 above].
+ * (eh, el) uses the six-operation TwoSum: |rl| may exceed |rh|, and TwoSum
+ * is exact for any order (equal to Fast2Sum wherever that one is exact).
+ * Valid for 2^-126 < |bh| < 2^126, where 1/bh is a normal number. */
+static void div22_accurate(float ah, float al, float bh, float bl, float *rh,
+                           float *rl)
+{
+    float th = 1.0f / bh;
+    float eh0 = fmaf(-bh, th, 1.0f);
+    float el0 = -bl * th;
+    float eh, el;
+    add12(eh0, el0, &eh, &el);
+    float dh, dl1;
+    mul12_fma(eh, th, &dh, &dl1);
+    float dl = fmaf(el, th, dl1);
+    float dh2, dl2;
+    fast_add12(dh, dl, &dh2, &dl2);
+    float sh, sl;
+    add12(dh2, th, &sh, &sl);
+    float v = dl2 + sl;
+    float mh, ml;
+    fast_add12(sh, v, &mh, &ml);
+    mul22_accurate(ah, al, mh, ml, rh, rl);
+}
+
 /* Mul22 theorem, with the final renormalisation of (t1, t3). */
 static void mul22(float ah, float al, float bh, float bl, int use_dekker,
                   float *rh, float *rl)
@@ -246,6 +300,20 @@ void oracle_div22(const float *ah, const float *al, const float *bh,
         div22(ah[i], al[i], bh[i], bl[i], use_dekker, &rh[i], &rl[i]);
 }
 
+void oracle_mul22_accurate(const float *ah, const float *al, const float *bh,
+                           const float *bl, float *rh, float *rl, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        mul22_accurate(ah[i], al[i], bh[i], bl[i], &rh[i], &rl[i]);
+}
+
+void oracle_div22_accurate(const float *ah, const float *al, const float *bh,
+                           const float *bl, float *rh, float *rl, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        div22_accurate(ah[i], al[i], bh[i], bl[i], &rh[i], &rl[i]);
+}
+
 void oracle_add22_accurate(const float *ah, const float *al, const float *bh,
                            const float *bl, float *rh, float *rl, int64_t n)
 {
@@ -262,7 +330,8 @@ void oracle_sub22_accurate(const float *ah, const float *al, const float *bh,
 
 /* Elementwise op selected by code: 0 add, 1 sub, 2 mul (FMA TwoProd),
  * 3 mul (Dekker TwoProd), 4 div (FMA TwoProd), 5 cancellation-safe add,
- * 6 cancellation-safe sub.  Used by the benchmark's CPU leg so that one call
+ * 6 cancellation-safe sub, 7 FMA-based product, 8 reciprocal-based
+ * division.  Used by the benchmark's CPU leg so that one call
  * times one operator over a sample. */
 int oracle_elementwise(int op, const float *ah, const float *al,
                        const float *bh, const float *bl, float *rh, float *rl,
@@ -276,6 +345,8 @@ int oracle_elementwise(int op, const float *ah, const float *al,
     case 4: oracle_div22(ah, al, bh, bl, rh, rl, n, 0); return 0;
     case 5: oracle_add22_accurate(ah, al, bh, bl, rh, rl, n); return 0;
     case 6: oracle_sub22_accurate(ah, al, bh, bl, rh, rl, n); return 0;
+    case 7: oracle_mul22_accurate(ah, al, bh, bl, rh, rl, n); return 0;
+    case 8: oracle_div22_accurate(ah, al, bh, bl, rh, rl, n); return 0;
     default: return -1;
     }
 }
@@ -599,7 +670,13 @@ static double la_to_double(long_acc *acc)
  *   op 1 Mul22: E = (ah + al)(bh + bl), bound = 2^-44 |E| (Mul22 theorem)
  *   op 2 Add12: E = ah + bh (al, bl unused), bound = 0 (Add12 theorem: exact)
  *   op 3 Mul12: E = ah * bh (al, bl unused), bound = 0 (Mul12 theorem: exact)
- * The error err = (rh + rl) - E is formed without rounding; then
+ *   op 4 Div22: quotient q = rh + rl of a / b, bound 2^-44 relative
+ *   op 5 FMA-based product (DWTimesDW3): as op 1, bound 5u^2 |E|
+ *   op 6 reciprocal-based division (DWDivDW3): as op 4, bound 9.8u^2
+ * For ops 0-3 and 5 the error err = (rh + rl) - E is formed without
+ * rounding.  For the divisions, E = ah + al (the dividend) and
+ * err = q (bh + bl) - E, also exact: |err| / |E| = |q - a/b| / |a/b| is the
+ * quotient's relative error.  Then
  *   rel[i]   = |err| / |E|    (0 if err = 0; +inf if E = 0 != err)
  *   ratio[i] = |err| / bound  (0 if err = 0; +inf if bound = 0 != err)
  * rounded to binary64.  Returns -1 for an unknown op. */
@@ -607,8 +684,9 @@ int oracle_ff_errors(int op, const float *ah, const float *al, const float *bh,
                      const float *bl, const float *rh, const float *rl,
                      int64_t n, double *rel, double *ratio)
 {
-    if (op < 0 || op > 3)
+    if (op < 0 || op > 6)
         return -1;
+    const int is_div = (op == 4 || op == 6);
     for (int64_t i = 0; i < n; ++i) {
         long_acc exact, lo;
         memset(&exact, 0, sizeof(exact));
@@ -623,6 +701,7 @@ int oracle_ff_errors(int op, const float *ah, const float *al, const float *bh,
             la_add_f32(&lo, bl[i], 1);
             break;
         case 1:
+        case 5:
             la_add_product(&exact, ah[i], bh[i]);
             la_add_product(&exact, ah[i], bl[i]);
             la_add_product(&exact, al[i], bh[i]);
@@ -632,15 +711,26 @@ int oracle_ff_errors(int op, const float *ah, const float *al, const float *bh,
             la_add_f32(&exact, ah[i], 1);
             la_add_f32(&exact, bh[i], 1);
             break;
-        default:
+        case 3:
             la_add_product(&exact, ah[i], bh[i]);
+            break;
+        default:
+            la_add_f32(&exact, ah[i], 1);
+            la_add_f32(&exact, al[i], 1);
             break;
         }
         long_acc err = exact;
         for (int k = 0; k < LA_LIMBS; ++k)
             err.limb[k] = -err.limb[k];
-        la_add_f32(&err, rh[i], 1);
-        la_add_f32(&err, rl[i], 1);
+        if (is_div) {
+            la_add_product(&err, rh[i], bh[i]);
+            la_add_product(&err, rh[i], bl[i]);
+            la_add_product(&err, rl[i], bh[i]);
+            la_add_product(&err, rl[i], bl[i]);
+        } else {
+            la_add_f32(&err, rh[i], 1);
+            la_add_f32(&err, rl[i], 1);
+        }
         double e = fabs(la_to_double(&err));
         double big = fabs(la_to_double(&exact));
         double bound = 0.0;
@@ -648,8 +738,12 @@ int oracle_ff_errors(int op, const float *ah, const float *al, const float *bh,
             double lo_mag = fabs(la_to_double(&lo));
             double b1 = ldexp(lo_mag, -24), b2 = ldexp(big, -44);
             bound = b1 > b2 ? b1 : b2;
-        } else if (op == 1) {
+        } else if (op == 1 || op == 4) {
             bound = ldexp(big, -44);
+        } else if (op == 5) {
+            bound = 5.0 * ldexp(big, -48);
+        } else if (op == 6) {
+            bound = 9.8 * ldexp(big, -48);
         }
         rel[i] = e == 0.0 ? 0.0 : (big == 0.0 ? INFINITY : e / big);
         ratio[i] = e == 0.0 ? 0.0 : (bound == 0.0 ? INFINITY : e / bound);

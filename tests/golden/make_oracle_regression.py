@@ -20,7 +20,7 @@ import ff_inputs as fi  # noqa: E402
 import oracle  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_regression.txt")
-OPS = ["add", "sub", "mul", "mul_dekker", "div"]
+OPS = ["add", "sub", "mul", "mul_dekker", "div", "add_accurate", "mul_accurate", "div_accurate"]
 
 
 def main():

@@ -52,7 +52,7 @@ def test_hand_derived_case(row):
 
 def test_oracle_regression_lock():
     rows = list(_rows("oracle_regression.txt"))
-    assert len(rows) == 800
+    assert len(rows) == 1280
     by_op = {}
     for op, ins, outs in rows:
         by_op.setdefault(op, []).append(([int(w, 16) for w in ins.split()],

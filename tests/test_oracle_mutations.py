@@ -13,6 +13,7 @@ import pytest
 import oracle
 import test_oracle_operators as OPS
 import test_oracle_accurate_add as ACC
+import test_oracle_accurate_mul_div as AMD
 import test_oracle_compensated as CMP
 import test_oracle_paper_tables as TAB
 import test_oracle_primitives as PRIM
@@ -60,6 +61,16 @@ ACC_PINS = [
     lambda: ACC.test_relative_error_bound_holds_under_cancellation("random"),
     lambda: ACC.test_relative_error_bound_holds_under_cancellation("gap"),
 ]
+AMD_PINS = [
+    AMD.test_mul_zero_low_words_is_the_exact_product_pair,
+    AMD.test_mul_identities,
+    AMD.test_div_identities,
+    AMD.test_hand_derived_cases,
+    lambda: AMD.test_mul_relative_error_bound("random"),
+    lambda: AMD.test_div_relative_error_bound("random"),
+    lambda: AMD.test_div_relative_error_bound("near"),
+    lambda: AMD.test_ff_errors_against_fractions("div22"),
+]
 CMP_PINS = [
     CMP.test_empty_and_single_terms,
     CMP.test_integer_data_is_exact,
@@ -99,6 +110,20 @@ MUTATIONS = [
     ("accurate_sign", "    float c = sl + th;", "    float c = sl - th;", ACC_PINS),
     ("accurate_low_pair", "    add12(al, bl, &th, &tl);", "    add12(al, bh, &th, &tl);", ACC_PINS),
     ("accurate_final_order", "    fast_add12(vh, w, rh, rl);", "    fast_add12(w, vh, rh, rl);", ACC_PINS),
+    ("mulacc_dropped_tl0", "    float tl1 = fmaf(ah, bl, tl0);", "    float tl1 = fmaf(ah, bl, 0.0f);",
+     AMD_PINS),
+    ("mulacc_wrong_index", "    float cl2 = fmaf(al, bh, tl1);", "    float cl2 = fmaf(al, bl, tl1);",
+     AMD_PINS),
+    ("mulacc_dropped_cl1", "    float cl3 = cl1 + cl2;", "    float cl3 = cl2;", AMD_PINS),
+    ("divacc_residual_sign", "    float el0 = -bl * th;", "    float el0 = bl * th;", AMD_PINS),
+    ("divacc_newton_sign", "    float eh0 = fmaf(-bh, th, 1.0f);", "    float eh0 = fmaf(bh, th, -1.0f);",
+     AMD_PINS),
+    ("divacc_dropped_low", "    float v = dl2 + sl;", "    float v = sl;", AMD_PINS),
+    ("divacc_dropped_ml", "    mul22_accurate(ah, al, mh, ml, rh, rl);",
+     "    mul22_accurate(ah, al, mh, 0.0f, rh, rl);", AMD_PINS),
+    ("divacc_dropped_el", "    float dl = fmaf(el, th, dl1);", "    float dl = dl1;", AMD_PINS),
+    ("errors_div_cross_term", "            la_add_product(&err, rl[i], bh[i]);\n",
+     "", AMD_PINS),
     ("dot2_dropped_product_error", "        s = s + (q + r);", "        s = s + q;", CMP_PINS),
     ("dot2_dropped_sum_error", "        s = s + (q + r);", "        s = s + r;", CMP_PINS),
     ("sum2_dropped_error", "        s = s + q;\n    }\n    out2[0] = p;\n    out2[1] = s;\n}\n\nvoid oracle_dot2",
