@@ -300,15 +300,21 @@ def main(argv=None) -> int:
     torch.cuda.synchronize()
     copy_ms = sum(s.elapsed_time(e) for s, e in copy_ev) / args.steps
     copy_gbs = 8 * n / (copy_ms * 1e-3) / 1e9
-    # The cancellation-safe addition on the same pairs (not part of the step).
-    acc_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
-    for s_ev, e_ev in acc_ev:
-        s_ev.record(stream)
-        ff.ff_add_accurate(a, b, out=r, stream=stream)
-        e_ev.record(stream)
-    torch.cuda.synchronize()
-    acc_ms = sum(s.elapsed_time(e) for s, e in acc_ev) / args.steps
+    # The tighter-bound operators on the same pairs (not part of the step).
+    accurate = {}
+    for name, fn in (("add", ff.ff_add_accurate), ("mul", ff.ff_mul_accurate),
+                     ("div", ff.ff_div_accurate)):
+        acc_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(args.steps)]
+        for s_ev, e_ev in acc_ev:
+            s_ev.record(stream)
+            fn(a, b, out=r, stream=stream)
+            e_ev.record(stream)
+        torch.cuda.synchronize()
+        acc_ms = sum(s.elapsed_time(e) for s, e in acc_ev) / args.steps
+        accurate[name] = {"ms": round(acc_ms, 5),
+                          "GB/s": round(BYTES_PER_FF_OP * n / (acc_ms * 1e-3) / 1e9, 1),
+                          "ff ops/s": n / (acc_ms * 1e-3)}
     per_op = {op: {"ms": round(kernel_ms[op], 5),
                    "GB/s": round(BYTES_PER_FF_OP * n / (kernel_ms[op] * 1e-3) / 1e9, 1)}
               for op in OPS}
@@ -344,9 +350,7 @@ def main(argv=None) -> int:
         "per_op": per_op,
         "copy_probe": {"ms": round(copy_ms, 5), "GB/s": round(copy_gbs, 1),
                        "bytes": 8 * n, "dominant_frac_of_copy": round(achieved / copy_gbs, 4)},
-        "add_accurate": {"ms": round(acc_ms, 5),
-                         "GB/s": round(BYTES_PER_FF_OP * n / (acc_ms * 1e-3) / 1e9, 1),
-                         "ff ops/s": n / (acc_ms * 1e-3)},
+        "accurate_ops": accurate,
     }
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle) on a bounded sample")

@@ -14,7 +14,7 @@ one JSON object per (operator, size) and a table.
 Inputs: binary32 x = +-2^t, t ~ U[-20, 20] (the high words of the base
 float-float generator, seeds 115031 / 115032 / 115033); float-float operands
 from the same generator.  Each launch's algorithmic bytes: Add / Mul 12,
-Mad / Add12 / Mul12 16, Add22 / Mul22 24 per element.
+Mad / Add12 / Mul12 16, the float-float operators 24 per element.
 """
 from __future__ import annotations
 
@@ -23,9 +23,10 @@ import json
 import sys
 
 OPS = ["Add", "Mul", "Mad", "Add12", "Mul12 (FMA)", "Mul12 (Dekker)", "Add22", "Mul22",
-       "Mul22 (Dekker)", "Add22 (accurate)"]
+       "Mul22 (Dekker)", "Div22", "Add22 (accurate)", "Mul22 (accurate)", "Div22 (accurate)"]
 BYTES = {"Add": 12, "Mul": 12, "Mad": 16, "Add12": 16, "Mul12 (FMA)": 16, "Mul12 (Dekker)": 16,
-         "Add22": 24, "Mul22": 24, "Mul22 (Dekker)": 24, "Add22 (accurate)": 24}
+         "Add22": 24, "Mul22": 24, "Mul22 (Dekker)": 24, "Div22": 24, "Add22 (accurate)": 24,
+         "Mul22 (accurate)": 24, "Div22 (accurate)": 24}
 
 
 def main(argv=None) -> int:
@@ -65,7 +66,10 @@ def main(argv=None) -> int:
             "Add22": lambda st=stream: ff.ff_add(Av, Bv, out=Rv, stream=st),
             "Mul22": lambda st=stream: ff.ff_mul(Av, Bv, out=Rv, stream=st),
             "Mul22 (Dekker)": lambda st=stream: ff.ff_mul_dekker(Av, Bv, out=Rv, stream=st),
+            "Div22": lambda st=stream: ff.ff_div(Av, Bv, out=Rv, stream=st),
             "Add22 (accurate)": lambda st=stream: ff.ff_add_accurate(Av, Bv, out=Rv, stream=st),
+            "Mul22 (accurate)": lambda st=stream: ff.ff_mul_accurate(Av, Bv, out=Rv, stream=st),
+            "Div22 (accurate)": lambda st=stream: ff.ff_div_accurate(Av, Bv, out=Rv, stream=st),
         }[op]
 
     # the first n words of each plane: every plane of A[:, :n] is contiguous

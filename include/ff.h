@@ -137,6 +137,32 @@ ff_status ff_sub_accurate(const float *a_hi, const float *a_lo,
                           const float *b_hi, const float *b_lo, float *r_hi,
                           float *r_lo, int64_t n, void *stream);
 
+/* FMA-based float-float product (not in the paper): r = a * b by the
+ * DWTimesDW3 algorithm of Joldes, Muller and Popescu (ACM TOMS 2017):
+ *   (ch, cl1) = TwoProd(a_hi, b_hi) (FMA); tl0 = a_lo (x) b_lo;
+ *   tl1 = fma(a_hi, b_lo, tl0); cl2 = fma(a_lo, b_hi, tl1);
+ *   cl3 = cl1 (+) cl2; (r_hi, r_lo) = Fast2Sum(ch, cl3).
+ * Relative error <= 5u^2 (u = 2^-24), against 2^-44 = 16u^2 for the paper's
+ * Mul22 (section 4.1, Mul22 theorem), in fewer operations.
+ * Arguments, layout and errors as for ff_add. */
+ff_status ff_mul_accurate(const float *a_hi, const float *a_lo,
+                          const float *b_hi, const float *b_lo, float *r_hi,
+                          float *r_lo, int64_t n, void *stream);
+
+/* Reciprocal-based float-float division (not in the paper): r = a / b by the
+ * DWDivDW3 algorithm of Joldes, Muller and Popescu (ACM TOMS 2017):
+ *   th = 1 (/) b_hi; e = (fma(-b_hi, th, 1), -b_lo (x) th) joined by Add12;
+ *   m = e * th + th (float-float times float, then plus float, each ending in
+ *   Fast2Sum); r = a * m by ff_mul_accurate's sequence.
+ * Relative error <= 9.8u^2.  One correctly rounded division per element
+ * (ff_div has two).  Valid for 2^-126 < |b_hi| < 2^126, where 1/b_hi is a
+ * normal number; outside, as for b = 0, the result is not a float-float
+ * quotient (no error is raised).
+ * Arguments, layout and errors as for ff_add. */
+ff_status ff_div_accurate(const float *a_hi, const float *a_lo,
+                          const float *b_hi, const float *b_lo, float *r_hi,
+                          float *r_lo, int64_t n, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Batched float-float dot products (reductions)                            */
 /* ------------------------------------------------------------------------ */

@@ -22,7 +22,7 @@ from ._lib import (GEMM_FMA_LOOP, GEMM_SLICED_BF16, GEMM_SLICED_I8, MATVEC_FAST,
 __all__ = [
     "lib", "FFError", "DotCfg", "build_info",
     "ff_add", "ff_sub", "ff_mul", "ff_mul_dekker", "ff_div", "ff_copy",
-    "ff_add_accurate", "ff_sub_accurate",
+    "ff_add_accurate", "ff_sub_accurate", "ff_mul_accurate", "ff_div_accurate",
     "ff_add12", "ff_mul12", "f32_add", "f32_mul", "f32_mad",
     "ff_dot_batched", "ff_dot_ff_batched", "ff_dot_batched_workspace_size",
     "ff_sum_batched", "ff_sum_ff_batched", "ff_dot2_batched", "ff_sum2_batched",
@@ -125,6 +125,19 @@ def ff_add_accurate(a, b, out=None, stream=None):
 def ff_sub_accurate(a, b, out=None, stream=None):
     """Cancellation-safe float-float difference a - b."""
     return _elementwise("ff_sub_accurate", a, b, out, stream)
+
+
+def ff_mul_accurate(a, b, out=None, stream=None):
+    """FMA-based float-float product (DWTimesDW3 of Joldes, Muller and
+    Popescu): relative error at most 5u^2, u = 2^-24."""
+    return _elementwise("ff_mul_accurate", a, b, out, stream)
+
+
+def ff_div_accurate(a, b, out=None, stream=None):
+    """Reciprocal-based float-float quotient a / b (DWDivDW3 of Joldes,
+    Muller and Popescu): relative error at most 9.8u^2, one division per
+    element; for 2^-126 < |b_hi| < 2^126."""
+    return _elementwise("ff_div_accurate", a, b, out, stream)
 
 
 def ff_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> torch.Tensor:

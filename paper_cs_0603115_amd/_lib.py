@@ -43,6 +43,8 @@ SIGNATURES = {
     "ff_div": _EW,
     "ff_add_accurate": _EW,
     "ff_sub_accurate": _EW,
+    "ff_mul_accurate": _EW,
+    "ff_div_accurate": _EW,
     "ff_copy": ([_P, _P, _i64, _P], _st),
     "ff_add12": ([_P, _P, _P, _P, _i64, _P], _st),
     "ff_mul12": ([_P, _P, _P, _P, _i64, _P], _st),

@@ -123,6 +123,50 @@ __device__ __forceinline__ void div22(float ah, float al, float bh, float bl,
     add12(c, cc, rh, rl);
 }
 
+// FMA-based product (not in the paper; its Mul22 bound is 2^-44 = 16u^2):
+// Joldes, Muller and Popescu's DWTimesDW3 (ACM TOMS 2017).  The three cross
+// products enter through two fused multiply-adds, smallest first, and one
+// Fast2Sum renormalises; relative error at most 5u^2, u = 2^-24.
+__device__ __forceinline__ void mul22_accurate(float ah, float al, float bh, float bl,
+                                               float &rh, float &rl)
+{
+    float ch, cl1;
+    mul12_fma(ah, bh, ch, cl1);
+    const float tl0 = al * bl;
+    const float tl1 = __builtin_fmaf(ah, bl, tl0);
+    const float cl2 = __builtin_fmaf(al, bh, tl1);
+    const float cl3 = cl1 + cl2;
+    fast_add12(ch, cl3, rh, rl);
+}
+
+// Reciprocal-based division (not in the paper): Joldes, Muller and
+// Popescu's DWDivDW3 (ACM TOMS 2017), relative error at most 9.8u^2.
+// th = 1/bh is refined by one Newton step into a float-float reciprocal m of
+// b: the residual e = 1 - b*th (its high part exact by one fma) times th,
+// plus th; the quotient is the product a*m above.  The residual's two words
+// are joined by the six-operation TwoSum, exact in either order of magnitude.
+// Valid for 2^-126 < |bh| < 2^126, where 1/bh is a normal number.
+__device__ __forceinline__ void div22_accurate(float ah, float al, float bh, float bl,
+                                               float &rh, float &rl)
+{
+    const float th = 1.0f / bh;
+    const float eh0 = __builtin_fmaf(-bh, th, 1.0f);
+    const float el0 = -bl * th;
+    float eh, el;
+    add12(eh0, el0, eh, el);
+    float dh, dl1;
+    mul12_fma(eh, th, dh, dl1);                 // (eh, el) * th ...
+    const float dl = __builtin_fmaf(el, th, dl1);
+    float dh2, dl2;
+    fast_add12(dh, dl, dh2, dl2);
+    float sh, sl;
+    add12(dh2, th, sh, sl);                     // ... + th
+    const float v = dl2 + sl;
+    float mh, ml;
+    fast_add12(sh, v, mh, ml);
+    mul22_accurate(ah, al, mh, ml, rh, rl);
+}
+
 // Butterfly all-reduce of a float-float value over the 64 lanes of a
 // wavefront: at distance m = 32, 16, ..., 1 every lane adds its partner's
 // value with Add22.  Add22 is commutative bit for bit (swapping the operands
@@ -146,7 +190,9 @@ enum Op : int {
     OP_MUL_DEKKER = 3,
     OP_DIV = 4,
     OP_ADD_ACCURATE = 5,
-    OP_SUB_ACCURATE = 6
+    OP_SUB_ACCURATE = 6,
+    OP_MUL_ACCURATE = 7,
+    OP_DIV_ACCURATE = 8
 };
 
 template <int OP>
@@ -165,8 +211,12 @@ __device__ __forceinline__ void apply(float ah, float al, float bh, float bl,
         div22(ah, al, bh, bl, rh, rl);
     else if constexpr (OP == OP_ADD_ACCURATE)
         add22_accurate(ah, al, bh, bl, rh, rl);
-    else
+    else if constexpr (OP == OP_SUB_ACCURATE)
         add22_accurate(ah, al, -bh, -bl, rh, rl);
+    else if constexpr (OP == OP_MUL_ACCURATE)
+        mul22_accurate(ah, al, bh, bl, rh, rl);
+    else
+        div22_accurate(ah, al, bh, bl, rh, rl);
 }
 
 } // namespace ffd

@@ -26,6 +26,8 @@ struct Mul22Dekker { static constexpr int op = ffd::OP_MUL_DEKKER; };
 struct Div22 { static constexpr int op = ffd::OP_DIV; };
 struct Add22Accurate { static constexpr int op = ffd::OP_ADD_ACCURATE; };
 struct Sub22Accurate { static constexpr int op = ffd::OP_SUB_ACCURATE; };
+struct Mul22Accurate { static constexpr int op = ffd::OP_MUL_ACCURATE; };
+struct Div22Accurate { static constexpr int op = ffd::OP_DIV_ACCURATE; };
 
 // Launch shape chosen by a sweep on MI355X over workgroup sizes 256-1024,
 // 1-8 float4 groups per thread, persistent grids, XCD-contiguous tile
@@ -231,6 +233,18 @@ ff_status ff_sub_accurate(const float *a_hi, const float *a_lo, const float *b_h
                           const float *b_lo, float *r_hi, float *r_lo, int64_t n, void *stream)
 {
     return elementwise<Sub22Accurate>(a_hi, a_lo, b_hi, b_lo, r_hi, r_lo, n, stream);
+}
+
+ff_status ff_mul_accurate(const float *a_hi, const float *a_lo, const float *b_hi,
+                          const float *b_lo, float *r_hi, float *r_lo, int64_t n, void *stream)
+{
+    return elementwise<Mul22Accurate>(a_hi, a_lo, b_hi, b_lo, r_hi, r_lo, n, stream);
+}
+
+ff_status ff_div_accurate(const float *a_hi, const float *a_lo, const float *b_hi,
+                          const float *b_lo, float *r_hi, float *r_lo, int64_t n, void *stream)
+{
+    return elementwise<Div22Accurate>(a_hi, a_lo, b_hi, b_lo, r_hi, r_lo, n, stream);
 }
 
 ff_status ff_copy(const float *src, float *dst, int64_t n, void *stream_ptr)

@@ -71,7 +71,8 @@ def test_status_strings():
     assert ff.lib.ff_last_error().decode() == ""
 
 
-EW = ["ff_add", "ff_sub", "ff_mul", "ff_mul_dekker", "ff_div", "ff_add_accurate", "ff_sub_accurate"]
+EW = ["ff_add", "ff_sub", "ff_mul", "ff_mul_dekker", "ff_div", "ff_add_accurate", "ff_sub_accurate",
+      "ff_mul_accurate", "ff_div_accurate"]
 
 
 @pytest.mark.parametrize("name", EW)

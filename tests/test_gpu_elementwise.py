@@ -16,7 +16,8 @@ from fpexact import mismatch_report, same_bits
 
 pytestmark = pytest.mark.gpu
 
-OPS = ["add", "sub", "mul", "mul_dekker", "div", "add_accurate", "sub_accurate"]
+OPS = ["add", "sub", "mul", "mul_dekker", "div", "add_accurate", "sub_accurate",
+       "mul_accurate", "div_accurate"]
 
 
 def _ff():
@@ -28,7 +29,8 @@ def gpu_op(op, a, b, out=None):
     ff = _ff()
     fn = {"add": ff.ff_add, "sub": ff.ff_sub, "mul": ff.ff_mul,
           "mul_dekker": ff.ff_mul_dekker, "div": ff.ff_div,
-          "add_accurate": ff.ff_add_accurate, "sub_accurate": ff.ff_sub_accurate}[op]
+          "add_accurate": ff.ff_add_accurate, "sub_accurate": ff.ff_sub_accurate,
+          "mul_accurate": ff.ff_mul_accurate, "div_accurate": ff.ff_div_accurate}[op]
     r = fn(a, b, out=out)
     torch.cuda.synchronize()
     return r
@@ -122,7 +124,7 @@ def test_repeat_runs_are_bitwise_identical():
         assert torch.equal(r1.view(torch.int32), r2.view(torch.int32))
 
 
-@pytest.mark.parametrize("op", ["add", "sub", "mul", "div", "add_accurate"])
+@pytest.mark.parametrize("op", ["add", "sub", "mul", "div", "add_accurate", "div_accurate"])
 def test_full_size_n2_28_bitexact(op):
     # the full operator-set workload: 2^28 pairs generated on the device, in
     # the launch configuration the benchmark times; every output word checked

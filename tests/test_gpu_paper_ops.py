@@ -5,9 +5,11 @@ measurement of section 6.1 (Table 5) on 2^24 random vectors.
 * Add12, Mul12 (FMA and Dekker) and binary32 add / multiply / fused
   multiply-add: bit-exact against the oracle at the paper's sizes
   2^12 .. 2^20, ragged tails, unaligned planes and in place.
-* Accuracy: the GPU results of Add12, Mul12, Add22 and Mul22 on 2^24 random
+* Accuracy: the GPU results of Add12, Mul12, Add22, Mul22 and Div22, and of
+  the FMA-based product and reciprocal-based division, on 2^24 random
   inputs, errors measured exactly by the oracle; Add12 and Mul12 must be
-  exact, Add22 within its theorem's bound, Mul22 within 2^-44 relative.  The
+  exact, Add22 within its theorem's bound, Mul22 and Div22 within 2^-44
+  relative, the other two within their published 5u^2 and 9.8u^2.  The
   measured maxima are printed (run with -s) and, when FF_REPORT_DIR is set,
   written there as JSON.
 """
@@ -163,8 +165,11 @@ def test_accuracy_error_free_transforms_2p24(op):
     assert np.all(ratio == 0.0), f"{op}: {int(np.count_nonzero(ratio))} inexact results"
 
 
-@pytest.mark.parametrize("op,workload", [("add22", "base"), ("mul22", "base"),
-                                         ("add22", "mixed"), ("mul22", "mixed")])
+FF_OPS = ["add22", "mul22", "div22", "mul22_accurate", "div22_accurate"]
+
+
+@pytest.mark.parametrize("workload", ["base", "mixed"])
+@pytest.mark.parametrize("op", FF_OPS)
 def test_accuracy_float_float_operators_2p24(op, workload):
     # base: x = +-2^t, t ~ U[-20, 20] split into (hi, lo); mixed: the
     # elementwise workload with 25 % cancellation and 10 % exponent-gap pairs
@@ -175,13 +180,16 @@ def test_accuracy_float_float_operators_2p24(op, workload):
         b = fi.base_ff(ACC_N, 115024, device="cuda")
     else:
         a, b, _ = fi.mixed_ff_pair(ACC_N, 115025, device="cuda")
-    r = ff.ff_add(a, b) if op == "add22" else ff.ff_mul(a, b)
+    fn = {"add22": ff.ff_add, "mul22": ff.ff_mul, "div22": ff.ff_div,
+          "mul22_accurate": ff.ff_mul_accurate, "div22_accurate": ff.ff_div_accurate}[op]
+    r = fn(a, b)
     torch.cuda.synchronize()
     an, bn, rn = a.cpu().numpy(), b.cpu().numpy(), r.cpu().numpy()
     rel, ratio = oracle.ff_errors(op, an[0], an[1], bn[0], bn[1], rn[0], rn[1])
     _report(f"{op}_{workload}", rel, ratio)
-    # the theorems' bounds hold for every input (Add22: max(2^-24 |al+bl|,
-    # 2^-44 |a+b|); Mul22: 2^-44 relative)
+    # each operator's bound holds for every input: Add22 max(2^-24 |al+bl|,
+    # 2^-44 |a+b|) (Add22 theorem); Mul22 and Div22 2^-44 relative; the
+    # FMA-based product 5u^2 and the reciprocal-based division 9.8u^2
     assert float(ratio.max()) <= 1.0
 
 
