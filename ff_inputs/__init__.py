@@ -24,6 +24,11 @@ them):
   * ``ill_conditioned_dot``: binary32 vectors whose dot product cancels to a
     prescribed condition number (the construction of Ogita, Rump and Oishi's
     test generator, 2005, section 6, written here from its description).
+  * ``binomial_poly`` / ``horner_points``: the expanded (x - 1)^n, whose
+    coefficients are exact binary32 integers for n <= 25, and points drawn
+    uniformly around its root (the ill-conditioned test polynomial of the
+    compensated Horner literature); ``random_poly``: normal(0,1)
+    coefficients, binary32 or float-float.
 """
 from __future__ import annotations
 
@@ -32,7 +37,7 @@ import torch
 __all__ = [
     "split_f64", "base_ff", "mixed_ff_pair", "batched_dot", "gaussian_ff",
     "gaussian_f32", "join_f64", "random_f32", "random_ff", "scaled_normal",
-    "ill_conditioned_dot",
+    "ill_conditioned_dot", "binomial_poly", "horner_points", "random_poly",
 ]
 
 
@@ -232,3 +237,30 @@ def ill_conditioned_dot(n: int, seed: int, log2_cond: float = 40.0, device="cpu"
     x = torch.cat([x1, x2])[perm].contiguous()
     y = torch.cat([y1, y2])[perm].contiguous()
     return x.to(device), y.to(device)
+
+
+def binomial_poly(n: int) -> torch.Tensor:
+    """Coefficients, ascending, of the expanded (x - 1)^n: a_i = C(n, i)
+    (-1)^(n - i).  Every one is an integer below 2^24, so binary32 holds it
+    exactly, for n <= 25."""
+    import math
+
+    if not 0 <= n <= 25:
+        raise ValueError("0 <= n <= 25")
+    return torch.tensor([math.comb(n, i) * (-1) ** (n - i) for i in range(n + 1)],
+                        dtype=torch.float32)
+
+
+def horner_points(n: int, seed: int, lo: float, hi: float, device="cpu") -> torch.Tensor:
+    """n binary32 points drawn uniformly from [lo, hi] (FP64 draws rounded)."""
+    g = _gen(seed, device)
+    u = torch.rand(n, generator=g, device=device, dtype=torch.float64)
+    return (lo + (hi - lo) * u).float()
+
+
+def random_poly(degree: int, seed: int, ff: bool = False) -> torch.Tensor:
+    """degree + 1 normal(0,1) coefficients: binary32 (shape (degree + 1,)),
+    or FP64 draws split into float-float (shape (2, degree + 1))."""
+    g = _gen(seed, "cpu")
+    a = torch.randn(degree + 1, generator=g, dtype=torch.float64)
+    return split_f64(a) if ff else a.float()

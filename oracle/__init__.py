@@ -82,6 +82,9 @@ _SIGS = {
     "oracle_dot2": ([_F, _F, _i64, _F], None),
     "oracle_sum2_batched": ([_F, _I64, _i64, _F], None),
     "oracle_dot2_batched": ([_F, _F, _I64, _i64, _F], None),
+    "oracle_horner_f32": ([_F, _int, _F, _F, _i64], None),
+    "oracle_horner_comp": ([_F, _int, _F, _F, _i64], None),
+    "oracle_horner_ff": ([_F, _F, _int, _F, _F, _F, _F, _i64], None),
     "oracle_ff_errors": ([_int, _F, _F, _F, _F, _F, _F, _i64, _D, _D], _int),
     "oracle_exact_dot": ([_F, _i64, _F, _i64, _i64, _I64], None),
     "oracle_exact_dot_ff": ([_F, _F, _i64, _F, _F, _i64, _i64, _I64], None),
@@ -283,6 +286,43 @@ def dot2_batched(x, y, offsets):
     out = np.empty(2 * (offs.size - 1), np.float32)
     lib().oracle_dot2_batched(_p(x), _p(y), _p(offs), offs.size - 1, _p(out))
     return out[0::2].copy(), out[1::2].copy()
+
+
+# ----------------------------------------------------- polynomial evaluation
+
+def _coefficients(a):
+    a = _f32(a).ravel()
+    if a.size == 0:
+        raise ValueError("a polynomial needs at least one coefficient")
+    return a, a.size - 1
+
+
+def horner_f32(a, x):
+    """Horner's rule in binary32 at every point of x; a[i] multiplies x^i."""
+    a, degree = _coefficients(a)
+    x = _f32(x).ravel()
+    y = np.empty(x.size, np.float32)
+    lib().oracle_horner_f32(_p(a), degree, _p(x), _p(y), x.size)
+    return y
+
+
+def horner_comp(a, x):
+    """Compensated Horner (Graillat, Langlois and Louvet) at every point."""
+    a, degree = _coefficients(a)
+    x = _f32(x).ravel()
+    y = np.empty(x.size, np.float32)
+    lib().oracle_horner_comp(_p(a), degree, _p(x), _p(y), x.size)
+    return y
+
+
+def horner_ff(ah, al, xh, xl):
+    """Float-float Horner (Mul22 then Add22 per step); returns (yh, yl)."""
+    (ah, al), _ = _pair_inputs(ah, al)
+    ah, degree = _coefficients(ah)
+    (xh, xl), n = _pair_inputs(xh, xl)
+    yh, yl = np.empty(n, np.float32), np.empty(n, np.float32)
+    lib().oracle_horner_ff(_p(ah), _p(al.ravel()), degree, _p(xh), _p(xl), _p(yh), _p(yl), n)
+    return yh, yl
 
 
 F32_REF_OPS = {"add": 0, "mul": 1, "mad": 2}

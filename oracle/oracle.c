@@ -490,6 +490,73 @@ void oracle_dot2_batched(const float *x, const float *y, const int64_t *offsets,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Polynomial evaluation: Horner's rule in binary32, compensated Horner,     */
+/* float-float Horner                                                        */
+/* ------------------------------------------------------------------------ */
+/*
+ * p(x) = sum_{i=0..degree} a[i] x^i, coefficients in ascending order, one
+ * evaluation per point.  Compensated algorithms are the paper's stated
+ * future work (section 7); CompHorner is that of Graillat, Langlois and
+ * Louvet ("Compensated Horner scheme", 2005; "Algorithms for accurate,
+ * validated and fast polynomial evaluation", 2009).
+ */
+
+/* Horner's rule: s = a_n; s = (s (x) x) (+) a_i for i = n-1 .. 0.  Two
+ * roundings per step (no fused multiply-add). */
+void oracle_horner_f32(const float *a, int32_t degree, const float *x,
+                       float *y, int64_t n)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        float s = a[degree];
+        for (int32_t i = degree - 1; i >= 0; --i)
+            s = (s * x[k]) + a[i];
+        y[k] = s;
+    }
+}
+
+/* CompHorner: Horner's rule with both rounding errors of every step caught
+ * by error-free transforms, (p, pi) = TwoProd(s, x) and
+ * (s, sigma) = TwoSum(p, a_i), and accumulated by a second Horner recurrence
+ * r = (r (x) x) (+) (pi (+) sigma), r_n = 0; the result is s_0 (+) r_0.
+ * Its error is at most u |p(x)| + gamma_2n^2 sum |a_i| |x|^i (u = 2^-24,
+ * gamma_k = k u / (1 - k u)) without underflow. */
+void oracle_horner_comp(const float *a, int32_t degree, const float *x,
+                        float *y, int64_t n)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        const float xk = x[k];
+        float s = a[degree];
+        float r = 0.0f;
+        for (int32_t i = degree - 1; i >= 0; --i) {
+            float p, pi, sigma;
+            mul12_fma(s, xk, &p, &pi);
+            add12(p, a[i], &s, &sigma);
+            r = (r * xk) + (pi + sigma);
+        }
+        y[k] = s + r;
+    }
+}
+
+/* Float-float Horner: s = a_n; s = Add22(Mul22(s, x), a_i), coefficients
+ * and points as float-float numbers (the paper's Add22 and Mul22 with FMA
+ * TwoProd, section 4.1). */
+void oracle_horner_ff(const float *ah, const float *al, int32_t degree,
+                      const float *xh, const float *xl, float *yh, float *yl,
+                      int64_t n)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        float sh = ah[degree], sl = al[degree];
+        for (int32_t i = degree - 1; i >= 0; --i) {
+            float ph, pl;
+            mul22(sh, sl, xh[k], xl[k], 0, &ph, &pl);
+            add22(ph, pl, ah[i], al[i], &sh, &sl);
+        }
+        yh[k] = sh;
+        yl[k] = sl;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Exact accumulation: a long fixed-point accumulator                       */
 /* ------------------------------------------------------------------------ */
 /*

@@ -15,6 +15,7 @@ import test_oracle_operators as OPS
 import test_oracle_accurate_add as ACC
 import test_oracle_accurate_mul_div as AMD
 import test_oracle_compensated as CMP
+import test_oracle_horner as HOR
 import test_oracle_paper_tables as TAB
 import test_oracle_primitives as PRIM
 import test_oracle_reductions as RED
@@ -71,6 +72,14 @@ AMD_PINS = [
     lambda: AMD.test_div_relative_error_bound("near"),
     lambda: AMD.test_ff_errors_against_fractions("div22"),
 ]
+HOR_PINS = [
+    HOR.test_degree_zero_returns_the_constant,
+    HOR.test_integer_polynomials_are_exact,
+    lambda: HOR.test_binomial_closed_form(7),
+    lambda: HOR.test_random_polynomials(8),
+    HOR.test_compensated_is_as_if_twice_the_precision,
+    HOR.test_float_float_coefficients_and_points,
+]
 CMP_PINS = [
     CMP.test_empty_and_single_terms,
     CMP.test_integer_data_is_exact,
@@ -124,6 +133,20 @@ MUTATIONS = [
     ("divacc_dropped_el", "    float dl = fmaf(el, th, dl1);", "    float dl = dl1;", AMD_PINS),
     ("errors_div_cross_term", "            la_add_product(&err, rl[i], bh[i]);\n",
      "", AMD_PINS),
+    ("horner_order", "            s = (s * x[k]) + a[i];", "            s = (s + a[i]) * x[k];", HOR_PINS),
+    ("horner_comp_dropped_pi", "            r = (r * xk) + (pi + sigma);",
+     "            r = (r * xk) + sigma;", HOR_PINS),
+    ("horner_comp_dropped_sigma", "            r = (r * xk) + (pi + sigma);",
+     "            r = (r * xk) + pi;", HOR_PINS),
+    ("horner_comp_unscaled_r", "            r = (r * xk) + (pi + sigma);",
+     "            r = r + (pi + sigma);", HOR_PINS),
+    ("horner_comp_no_correction", "        y[k] = s + r;", "        y[k] = s;", HOR_PINS),
+    ("horner_ff_coefficient_lo", "            add22(ph, pl, ah[i], al[i], &sh, &sl);",
+     "            add22(ph, pl, ah[i], 0.0f, &sh, &sl);", HOR_PINS),
+    ("horner_ff_point_lo", "            mul22(sh, sl, xh[k], xl[k], 0, &ph, &pl);",
+     "            mul22(sh, sl, xh[k], 0.0f, 0, &ph, &pl);", HOR_PINS),
+    ("horner_ff_top_lo", "        float sh = ah[degree], sl = al[degree];",
+     "        float sh = ah[degree], sl = 0.0f;", HOR_PINS),
     ("dot2_dropped_product_error", "        s = s + (q + r);", "        s = s + q;", CMP_PINS),
     ("dot2_dropped_sum_error", "        s = s + (q + r);", "        s = s + r;", CMP_PINS),
     ("sum2_dropped_error", "        s = s + q;\n    }\n    out2[0] = p;\n    out2[1] = s;\n}\n\nvoid oracle_dot2",
