@@ -28,6 +28,12 @@ if _ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_FF_OP = 24           # 4 binary32 words in, 2 out
+# binary32 VALU rate: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6 T adds,
+# multiplies or fused multiply-adds per second (the published 157.3 TFLOP/s
+# counts a fused multiply-add as two).  A wave64 binary32 instruction issues
+# in two cycles: the compensated Horner loop, 11 such instructions per point
+# and step and no packed ones, averages 2.8 cycles per instruction.
+ALU_PEAK_OPS = 256 * 4 * 32 * 2.4e9
 OPS = ["add", "sub", "mul", "div"]
 
 
@@ -86,12 +92,13 @@ def parse_args(argv=None):
     return p.parse_args(argv)
 
 
-def _time_launches(fn, reps: int, stream) -> float:
+def _time_launches(fn, reps: int, stream, warmup: int = 1) -> float:
     """Mean milliseconds per call of fn() over reps calls, HIP events on the
-    launch stream (one untimed call first)."""
+    launch stream (warmup untimed calls first)."""
     import torch
 
-    fn()
+    for _ in range(warmup):
+        fn()
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record(stream)
@@ -138,6 +145,30 @@ def secondary(stream) -> dict:
                        "flushed_ff_ops/s": n / (cold_ms * 1e-3)}
     out["elementwise_2p20"] = small
     del a, b, r, flush
+    torch.cuda.empty_cache()
+
+    n, deg = 1 << 26, 25
+    log(f"[bench] polynomial evaluation: (x - 1)^{deg} expanded at 2^26 points")
+    coef = fi.binomial_poly(deg).to(dev)
+    x = fi.horner_points(n, 115041, 0.75, 1.25, device=dev)
+    y = torch.empty_like(x)
+    yff = ff.ff_empty((n,), device=dev)
+    horner = {"points": n, "degree": deg}
+    # floating-point operations per point and degree: mul + add; TwoProd 2 +
+    # TwoSum 6 + correction 3; Mul22 12 + Add22 11
+    for name, fn, per_step in (
+            ("horner_f32", lambda: ff.ff_horner_f32(coef, x, out=y, stream=stream), 2),
+            ("horner_comp", lambda: ff.ff_horner_comp(coef, x, out=y, stream=stream), 11),
+            ("horner_ff", lambda: ff.ff_horner_ff(coef, x, out=yff, stream=stream,
+                                                  ff_points=False), 23)):
+        # ALU-bound: ~100 ms of the same launches first, so that the clock
+        # has ramped up before the timed ones
+        ms = _time_launches(fn, 50, stream, warmup=max(10, int(0.1 / (per_step * deg * n / ALU_PEAK_OPS))))
+        ops = per_step * deg * n / (ms * 1e-3)
+        horner[name] = {"ms": round(ms, 4), "Gpoints/s": round(n / (ms * 1e-3) / 1e9, 2),
+                        "fp32_ops/s": ops, "alu_frac": round(ops / ALU_PEAK_OPS, 4)}
+    out["horner_2p26"] = horner
+    del coef, x, y, yff
     torch.cuda.empty_cache()
 
     log("[bench] batched dot: 4096 vectors, lengths floor(2^U[6,20])")

@@ -424,6 +424,47 @@ ff_status ff_f32_mul(const float *a, const float *b, float *r, int64_t n,
 ff_status ff_f32_mad(const float *a, const float *b, const float *c, float *r,
                      int64_t n, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Polynomial evaluation at many points (compensated algorithms, the        */
+/* paper's future work, section 7)                                           */
+/* ------------------------------------------------------------------------ */
+/*
+ * p(x) = sum_{i=0..degree} coef[i] x^i, coefficients in ascending order
+ * (device memory, degree + 1 words per plane), evaluated independently at
+ * each of the n points x_k; result k goes to y_k.
+ *
+ *   ff_horner_f32   Horner's rule in binary32: s = c_n; s = (s (x) x) (+) c_i.
+ *                   Error <= gamma_2n(u) sum |c_i| |x|^i, u = 2^-24,
+ *                   gamma_k(v) = k v / (1 - k v).
+ *   ff_horner_comp  compensated Horner (CompHorner of Graillat, Langlois and
+ *                   Louvet, 2005): (p, pi) = TwoProd(s, x) (FMA);
+ *                   (s, sigma) = Add12(p, c_i); r = (r (x) x) (+) (pi (+)
+ *                   sigma), r starting at 0; y = s (+) r.  Error <= u |p(x)|
+ *                   + gamma_2n(u)^2 sum |c_i| |x|^i: as accurate as Horner in
+ *                   twice the working precision, then rounded.
+ *   ff_horner_ff    float-float Horner: s = (coef_hi[n], coef_lo[n]);
+ *                   s = Add22(Mul22(s, x), c_i) (section 4.1 operators, FMA
+ *                   TwoProd); the result is the float-float (y_hi, y_lo).
+ *                   Error <= gamma_2n(2^-44) sum |c_i| |x|^i.
+ * The bounds assume no underflow or overflow.  Results are bit-for-bit
+ * those of the operation sequences above (no contraction, IEEE binary32).
+ *
+ * Arguments: coef / coef_hi (non-null) and coef_lo (null: zero low words);
+ * x / x_hi (non-null) and x_lo (null: binary32 points); y / y_hi, y_lo
+ * (non-null).  All device pointers, caller-owned, 4-byte aligned; the float4
+ * path runs when every point and result plane is 16-byte aligned.  A result
+ * plane may alias a point plane exactly (in place); coefficients must not
+ * alias a result.
+ * Errors: FF_ERR_NULL, FF_ERR_SIZE (degree < 0 or n < 0), FF_ERR_ALIGN,
+ * FF_ERR_HIP.  n = 0 is a no-op. */
+ff_status ff_horner_f32(const float *coef, int32_t degree, const float *x,
+                        float *y, int64_t n, void *stream);
+ff_status ff_horner_comp(const float *coef, int32_t degree, const float *x,
+                         float *y, int64_t n, void *stream);
+ff_status ff_horner_ff(const float *coef_hi, const float *coef_lo,
+                       int32_t degree, const float *x_hi, const float *x_lo,
+                       float *y_hi, float *y_lo, int64_t n, void *stream);
+
 /* dst[i] = src[i] for i < n (binary32), with the same load/store pattern as
  * the elementwise operators: the HBM bandwidth reference for roofline and
  * counter calibration.  Errors as for the elementwise operators. */

@@ -24,6 +24,7 @@ __all__ = [
     "ff_add", "ff_sub", "ff_mul", "ff_mul_dekker", "ff_div", "ff_copy",
     "ff_add_accurate", "ff_sub_accurate", "ff_mul_accurate", "ff_div_accurate",
     "ff_add12", "ff_mul12", "f32_add", "f32_mul", "f32_mad",
+    "ff_horner_f32", "ff_horner_comp", "ff_horner_ff",
     "ff_dot_batched", "ff_dot_ff_batched", "ff_dot_batched_workspace_size",
     "ff_sum_batched", "ff_sum_ff_batched", "ff_dot2_batched", "ff_sum2_batched",
     "ff_matvec", "ff_matvec_backward", "ff_dot_backward", "MATVEC_FAST", "MATVEC_PLAIN",
@@ -232,6 +233,82 @@ def f32_mad(a, b, c, out=None, stream=None) -> torch.Tensor:
     with torch.cuda.device(a.device):
         check("ff_f32_mad", lib.ff_f32_mad(_ptr(a), _ptr(b), _ptr(c), _ptr(out), a.numel(),
                                            _stream_handle(stream)))
+    return out
+
+
+# ------------------------------------------------------- polynomial evaluation
+
+def _coefficients(name: str, coef: torch.Tensor, ff: bool):
+    """Device pointers (hi, lo or None) and degree of a coefficient tensor:
+    binary32 (degree + 1,) or, when ff is allowed, float-float (2, degree + 1)."""
+    if not isinstance(coef, torch.Tensor) or coef.dtype != torch.float32 or not coef.is_cuda:
+        raise TypeError(f"{name}: coefficients must be a float32 tensor on a HIP device")
+    if coef.dim() == 1:
+        if not coef.is_contiguous():
+            raise ValueError(f"{name}: coefficients must be contiguous")
+        hi, lo, count = coef, None, coef.numel()
+    elif ff and coef.dim() == 2 and coef.shape[0] == 2:
+        _check_ff(coef, "coef")
+        hi, lo, count = coef[0], coef[1], coef.shape[1]
+    else:
+        raise ValueError(f"{name}: coefficients of shape {tuple(coef.shape)}")
+    if count < 1:
+        raise ValueError(f"{name}: a polynomial needs at least one coefficient")
+    return _ptr(hi), (None if lo is None else _ptr(lo)), count - 1
+
+
+def _horner_f32(name, coef, x, out, stream):
+    ch, _, degree = _coefficients(name, coef, ff=False)
+    _f32_operands(name, x)
+    if coef.device != x.device:
+        raise ValueError(f"{name}: coefficients and points on different devices")
+    out = torch.empty_like(x) if out is None else out
+    _f32_operands(name, x, out)
+    with torch.cuda.device(x.device):
+        check(name, getattr(lib, name)(ch, degree, _ptr(x), _ptr(out), x.numel(),
+                                       _stream_handle(stream)))
+    return out
+
+
+def ff_horner_f32(coef, x, out=None, stream=None) -> torch.Tensor:
+    """Horner's rule in binary32: sum_i coef[i] x^i at every point of x."""
+    return _horner_f32("ff_horner_f32", coef, x, out, stream)
+
+
+def ff_horner_comp(coef, x, out=None, stream=None) -> torch.Tensor:
+    """Compensated Horner (Graillat, Langlois and Louvet) at every point of
+    x: binary32 results as accurate as Horner's rule in twice the working
+    precision, rounded once."""
+    return _horner_f32("ff_horner_comp", coef, x, out, stream)
+
+
+def ff_horner_ff(coef, x, out=None, stream=None, ff_points: bool = True) -> torch.Tensor:
+    """Float-float Horner (Mul22 then Add22 per step).  coef: binary32
+    (degree + 1,) or float-float (2, degree + 1); x: a float-float tensor
+    (2, ...) of points, or with ff_points=False binary32 points of any shape.
+    Returns a float-float tensor (2, *points shape)."""
+    name = "ff_horner_ff"
+    ch, cl, degree = _coefficients(name, coef, ff=True)
+    if ff_points:
+        _check_ff(x, "x")
+        xh, xl = _planes(x)
+        shape = tuple(x.shape[1:])
+    else:
+        _f32_operands(name, x)
+        xh, xl, shape = _ptr(x), None, tuple(x.shape)
+    dev = coef.device
+    if x.device != dev:
+        raise ValueError(f"{name}: coefficients and points on different devices")
+    out = ff_empty(shape, device=dev) if out is None else out
+    _check_ff(out, "out")
+    if tuple(out.shape) != (2, *shape) or out.device != dev:
+        raise ValueError(f"{name}: out must have shape {(2, *shape)} on {dev}")
+    n = 1
+    for d in shape:
+        n *= d
+    with torch.cuda.device(dev):
+        check(name, lib.ff_horner_ff(ch, cl, degree, xh, xl, *_planes(out), n,
+                                     _stream_handle(stream)))
     return out
 
 

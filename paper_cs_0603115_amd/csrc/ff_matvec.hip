@@ -5,7 +5,7 @@
 // forward pass reads A once (8 bytes per element) and performs Mul22 + Add22
 // (~26 VALU) per element; the fused backward reads A once and writes dA once
 // (16 bytes per element) with Mul22 (dA) + Mul22 + Add22 (dx) (~38 VALU).
-// Both are HBM-bound on gfx950 (ridge ~4.9 lane-ops per byte).
+// Both are HBM-bound on gfx950 (ridge ~9.8 binary32 operations per byte).
 //
 // Fast forward: one workgroup per row; lane t takes float4 groups t,
 // t + BLOCK, ... of the row (coalesced 1 KiB per wavefront load), keeps four

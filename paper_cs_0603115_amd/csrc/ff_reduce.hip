@@ -14,8 +14,8 @@
 // issuing XCD, which per chunk cost more than the chunk's own traffic.
 //
 // Per element the binary32 path reads 8 bytes and performs TwoProd (2 VALU)
-// plus Add22 (~14 VALU): ~2 operations per byte, under the ~4.9 ops/byte
-// ridge of gfx950 (39.3 T lane-ops/s unpacked FP32 over 8 TB/s), so the
+// plus Add22 (~14 VALU): ~2 operations per byte, under the ~9.8 ops/byte
+// ridge of gfx950 (78.6 T binary32 operations/s over 8 TB/s), so the
 // partials launch is HBM-bound.  The float-float path reads 16 bytes and
 // performs Mul22 + Add22 (~27 VALU) per element.
 //

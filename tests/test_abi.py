@@ -108,6 +108,36 @@ def test_stream_operator_validation(name, nptr):
         assert fn(*q, 10, None) == ERR_ALIGN
 
 
+@pytest.mark.parametrize("name", ["ff_horner_f32", "ff_horner_comp"])
+def test_horner_validation(name):
+    fn = getattr(ff.lib, name)
+    c, x, y = 4096, 8192, 12288
+    assert fn(c, -1, x, y, 10, None) == ERR_SIZE
+    assert fn(c, 3, x, y, -1, None) == ERR_SIZE
+    assert fn(None, 3, None, None, 0, None) == 0    # n = 0: no-op
+    for q in ((None, x, y), (c, None, y), (c, x, None)):
+        assert fn(q[0], 3, q[1], q[2], 10, None) == ERR_NULL
+    for q in ((c + 2, x, y), (c, x + 2, y), (c, x, y + 2)):
+        assert fn(q[0], 3, q[1], q[2], 10, None) == ERR_ALIGN
+
+
+def test_horner_ff_validation():
+    fn = ff.lib.ff_horner_ff
+    p = [4096 * (k + 1) for k in range(6)]          # ch, cl, xh, xl, yh, yl
+    call = lambda q, degree=3, n=10: fn(q[0], q[1], degree, q[2], q[3], q[4], q[5], n, None)
+    assert call(p, degree=-2) == ERR_SIZE
+    assert call(p, n=-1) == ERR_SIZE
+    assert call([None] * 6, n=0) == 0
+    for k in (0, 2, 4, 5):                          # coefficient and point low words may be null
+        q = list(p)
+        q[k] = None
+        assert call(q) == ERR_NULL
+    for k in range(6):
+        q = list(p)
+        q[k] = p[k] + 2
+        assert call(q) == ERR_ALIGN
+
+
 def test_copy_validation():
     assert ff.lib.ff_copy(4096, 8192, -3, None) == ERR_SIZE
     assert ff.lib.ff_copy(4096, 8192, 0, None) == 0
