@@ -82,6 +82,8 @@ _SIGS = {
     "oracle_dot2": ([_F, _F, _i64, _F], None),
     "oracle_sum2_batched": ([_F, _I64, _i64, _F], None),
     "oracle_dot2_batched": ([_F, _F, _I64, _i64, _F], None),
+    "oracle_from_f64": ([_D, _F, _F, _i64], None),
+    "oracle_to_f64": ([_F, _F, _D, _i64], None),
     "oracle_horner_f32": ([_F, _int, _F, _F, _i64], None),
     "oracle_horner_comp": ([_F, _int, _F, _F, _i64], None),
     "oracle_horner_ff": ([_F, _F, _int, _F, _F, _F, _F, _i64], None),
@@ -286,6 +288,24 @@ def dot2_batched(x, y, offsets):
     out = np.empty(2 * (offs.size - 1), np.float32)
     lib().oracle_dot2_batched(_p(x), _p(y), _p(offs), offs.size - 1, _p(out))
     return out[0::2].copy(), out[1::2].copy()
+
+
+# --------------------------------------------------------------- conversions
+
+def from_f64(x):
+    """binary64 -> float-float: hi = fl32(x), lo = fl32(x - hi)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    hi, lo = np.empty(x.size, np.float32), np.empty(x.size, np.float32)
+    lib().oracle_from_f64(_p(x), _p(hi), _p(lo), x.size)
+    return hi, lo
+
+
+def to_f64(hi, lo):
+    """float-float -> binary64: (double) hi + (double) lo, one rounding."""
+    (hi, lo), n = _pair_inputs(hi, lo)
+    x = np.empty(n, np.float64)
+    lib().oracle_to_f64(_p(hi), _p(lo), _p(x), n)
+    return x
 
 
 # ----------------------------------------------------- polynomial evaluation

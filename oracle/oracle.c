@@ -328,6 +328,27 @@ void oracle_sub22_accurate(const float *ah, const float *al, const float *bh,
         add22_accurate(ah[i], al[i], -bh[i], -bl[i], &rh[i], &rl[i]);
 }
 
+/* Conversions between binary64 and float-float (not in the paper, whose
+ * inputs are float-float already).  From binary64: hi = fl32(x) and
+ * lo = fl32(x - hi); x - hi is exact in binary64 (hi is x rounded to 24
+ * bits), so hi + lo is x to within 2^-48 |x|, for |x| below the binary32
+ * overflow threshold.  To binary64: (double) hi + (double) lo, one binary64
+ * rounding (exact whenever the pair's bits fit in 53). */
+void oracle_from_f64(const double *x, float *hi, float *lo, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        float h = (float)x[i];
+        hi[i] = h;
+        lo[i] = (float)(x[i] - (double)h);
+    }
+}
+
+void oracle_to_f64(const float *hi, const float *lo, double *x, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        x[i] = (double)hi[i] + (double)lo[i];
+}
+
 /* Elementwise op selected by code: 0 add, 1 sub, 2 mul (FMA TwoProd),
  * 3 mul (Dekker TwoProd), 4 div (FMA TwoProd), 5 cancellation-safe add,
  * 6 cancellation-safe sub, 7 FMA-based product, 8 reciprocal-based

@@ -15,6 +15,7 @@ import test_oracle_operators as OPS
 import test_oracle_accurate_add as ACC
 import test_oracle_accurate_mul_div as AMD
 import test_oracle_compensated as CMP
+import test_oracle_convert as CNV
 import test_oracle_horner as HOR
 import test_oracle_paper_tables as TAB
 import test_oracle_primitives as PRIM
@@ -79,6 +80,12 @@ HOR_PINS = [
     lambda: HOR.test_random_polynomials(8),
     HOR.test_compensated_is_as_if_twice_the_precision,
     HOR.test_float_float_coefficients_and_points,
+]
+CNV_PINS = [
+    CNV.test_from_f64_rounds_hi_and_keeps_48_bits,
+    CNV.test_from_f64_of_binary32_values_is_exact,
+    CNV.test_to_f64_rounds_once,
+    CNV.test_round_trip_where_the_bits_fit,
 ]
 CMP_PINS = [
     CMP.test_empty_and_single_terms,
@@ -147,6 +154,10 @@ MUTATIONS = [
      "            mul22(sh, sl, xh[k], 0.0f, 0, &ph, &pl);", HOR_PINS),
     ("horner_ff_top_lo", "        float sh = ah[degree], sl = al[degree];",
      "        float sh = ah[degree], sl = 0.0f;", HOR_PINS),
+    ("from_f64_low_word_in_binary32", "        lo[i] = (float)(x[i] - (double)h);",
+     "        lo[i] = (float)x[i] - h;", CNV_PINS),
+    ("to_f64_binary32_sum", "        x[i] = (double)hi[i] + (double)lo[i];",
+     "        x[i] = (double)(hi[i] + lo[i]);", CNV_PINS),
     ("dot2_dropped_product_error", "        s = s + (q + r);", "        s = s + q;", CMP_PINS),
     ("dot2_dropped_sum_error", "        s = s + (q + r);", "        s = s + r;", CMP_PINS),
     ("sum2_dropped_error", "        s = s + q;\n    }\n    out2[0] = p;\n    out2[1] = s;\n}\n\nvoid oracle_dot2",
