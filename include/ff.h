@@ -465,6 +465,25 @@ ff_status ff_horner_ff(const float *coef_hi, const float *coef_lo,
                        int32_t degree, const float *x_hi, const float *x_lo,
                        float *y_hi, float *y_lo, int64_t n, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Conversions between binary64 and float-float (not in the paper)          */
+/* ------------------------------------------------------------------------ */
+/*
+ * ff_from_f64: hi_i = fl32(x_i), lo_i = fl32(x_i - hi_i) (the difference is
+ *   exact in binary64), so hi + lo = x to within 2^-48 |x| for x in the
+ *   binary32 normal range; |x| beyond the binary32 range gives hi = +-inf.
+ * ff_to_f64: x_i = (double) hi_i + (double) lo_i, one binary64 rounding
+ *   (exact whenever the pair's bits fit in 53).
+ * Pointers: device, caller-owned; binary64 plane 8-byte aligned, binary32
+ * planes 4-byte aligned (16-byte alignment of all three selects the
+ * four-per-lane path).  No aliasing between the binary64 and binary32 planes.
+ * Errors: FF_ERR_SIZE (n < 0), FF_ERR_NULL, FF_ERR_ALIGN, FF_ERR_HIP.
+ * n = 0 is a no-op. */
+ff_status ff_from_f64(const double *x, float *hi, float *lo, int64_t n,
+                      void *stream);
+ff_status ff_to_f64(const float *hi, const float *lo, double *x, int64_t n,
+                    void *stream);
+
 /* dst[i] = src[i] for i < n (binary32), with the same load/store pattern as
  * the elementwise operators: the HBM bandwidth reference for roofline and
  * counter calibration.  Errors as for the elementwise operators. */

@@ -29,7 +29,8 @@ __all__ = [
     "ff_sum_batched", "ff_sum_ff_batched", "ff_dot2_batched", "ff_sum2_batched",
     "ff_matvec", "ff_matvec_backward", "ff_dot_backward", "MATVEC_FAST", "MATVEC_PLAIN",
     "ff_gemm", "ff_gemm_workspace_size", "GEMM_FMA_LOOP", "GEMM_SLICED_BF16", "GEMM_SLICED_I8",
-    "ff_empty", "ff_zeros",
+    "ff_empty", "ff_zeros", "ff_from_f64", "ff_to_f64",
+    "add", "sub", "mul", "div", "dot_batched", "gemm", "matvec", "from_float64", "to_float64",
 ]
 
 
@@ -233,6 +234,40 @@ def f32_mad(a, b, c, out=None, stream=None) -> torch.Tensor:
     with torch.cuda.device(a.device):
         check("ff_f32_mad", lib.ff_f32_mad(_ptr(a), _ptr(b), _ptr(c), _ptr(out), a.numel(),
                                            _stream_handle(stream)))
+    return out
+
+
+# ----------------------------------------------------------------- conversions
+
+def ff_from_f64(x: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    """binary64 tensor -> float-float tensor (2, *x.shape): hi = fl32(x),
+    lo = fl32(x - hi), on the device."""
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.float64 or not x.is_cuda:
+        raise TypeError("ff_from_f64: expected a float64 tensor on a HIP device")
+    if not x.is_contiguous():
+        raise ValueError("ff_from_f64: x must be contiguous")
+    out = ff_empty(x.shape, device=x.device) if out is None else out
+    _check_ff(out, "out")
+    if tuple(out.shape) != (2, *x.shape) or out.device != x.device:
+        raise ValueError(f"ff_from_f64: out must have shape {(2, *x.shape)} on {x.device}")
+    with torch.cuda.device(x.device):
+        check("ff_from_f64", lib.ff_from_f64(_ptr(x), *_planes(out), x.numel(),
+                                             _stream_handle(stream)))
+    return out
+
+
+def ff_to_f64(a: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+    """float-float tensor -> binary64 tensor: (double) hi + (double) lo, one
+    rounding, on the device."""
+    _check_ff(a, "a")
+    shape = tuple(a.shape[1:])
+    out = torch.empty(shape, dtype=torch.float64, device=a.device) if out is None else out
+    if not isinstance(out, torch.Tensor) or out.dtype != torch.float64 or \
+            tuple(out.shape) != shape or out.device != a.device or not out.is_contiguous():
+        raise ValueError(f"ff_to_f64: out must be a contiguous float64 tensor of shape {shape}")
+    with torch.cuda.device(a.device):
+        check("ff_to_f64", lib.ff_to_f64(*_planes(a), _ptr(out), out.numel(),
+                                         _stream_handle(stream)))
     return out
 
 
@@ -592,3 +627,10 @@ def ff_gemm(A: torch.Tensor, B: torch.Tensor, algo: int = GEMM_SLICED_I8, out=No
                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                      _stream_handle(stream)))
     return out
+
+
+# Short names of the Python surface: float-float tensors in, float-float
+# tensors out.
+add, sub, mul, div = ff_add, ff_sub, ff_mul, ff_div
+dot_batched, gemm, matvec = ff_dot_batched, ff_gemm, ff_matvec
+from_float64, to_float64 = ff_from_f64, ff_to_f64

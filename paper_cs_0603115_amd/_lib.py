@@ -70,6 +70,8 @@ SIGNATURES = {
     "ff_matvec_backward": ([_i64, _i64, _P, _P, _i64, _P, _P, _P, _P, _P, _P, _i64, _P, _P, _i32,
                             _P, _sz, _P], _st),
     "ff_dot_backward": ([_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _i64, _P], _st),
+    "ff_from_f64": ([_P, _P, _P, _i64, _P], _st),
+    "ff_to_f64": ([_P, _P, _P, _i64, _P], _st),
     "ff_horner_f32": ([_P, _i32, _P, _P, _i64, _P], _st),
     "ff_horner_comp": ([_P, _i32, _P, _P, _i64, _P], _st),
     "ff_horner_ff": ([_P, _P, _i32, _P, _P, _P, _P, _i64, _P], _st),

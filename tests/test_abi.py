@@ -138,6 +138,21 @@ def test_horner_ff_validation():
         assert call(q) == ERR_ALIGN
 
 
+@pytest.mark.parametrize("name", ["ff_from_f64", "ff_to_f64"])
+def test_conversion_validation(name):
+    fn = getattr(ff.lib, name)
+    f64 = 4096
+    f32 = (8192, 12288)
+    call = (lambda d, h, l, n: fn(d, h, l, n, None)) if name == "ff_from_f64" else \
+        (lambda d, h, l, n: fn(h, l, d, n, None))
+    assert call(f64, *f32, -1) == ERR_SIZE
+    assert call(None, None, None, 0) == 0
+    assert call(None, *f32, 5) == ERR_NULL
+    assert call(f64, None, f32[1], 5) == ERR_NULL
+    assert call(f64 + 4, *f32, 5) == ERR_ALIGN          # binary64 plane needs 8 bytes
+    assert call(f64, f32[0] + 2, f32[1], 5) == ERR_ALIGN
+
+
 def test_copy_validation():
     assert ff.lib.ff_copy(4096, 8192, -3, None) == ERR_SIZE
     assert ff.lib.ff_copy(4096, 8192, 0, None) == 0

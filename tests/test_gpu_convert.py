@@ -1,0 +1,69 @@
+"""GPU parity of the binary64 <-> float-float conversions: every word bit
+for bit against the oracle, on wide exponent ranges (low words down to the
+subnormal range, signed zeros), ragged sizes, unaligned planes (the
+one-per-lane kernel) and a 2^24-element run; the Python short names are the
+same entry points."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import ff_inputs as fi
+import oracle
+from fpexact import mismatch_report, same_bits
+
+pytestmark = pytest.mark.gpu
+
+
+def _ff():
+    import paper_cs_0603115_amd as ff
+    return ff
+
+
+def _f64(n, seed, emin=-120, emax=120):
+    rng = np.random.default_rng(seed)
+    m = rng.uniform(1.0, 2.0, n) * rng.choice([-1.0, 1.0], n)
+    x = np.ldexp(m, rng.integers(emin, emax + 1, n))
+    x[:: 97] = 0.0
+    x[1:: 97] = -0.0
+    return x
+
+
+@pytest.mark.parametrize("n", [1, 3, 5, 1027, 4099, (1 << 16) + 7, 1 << 24])
+def test_from_and_to_f64_bitexact(n):
+    print(f"[gpu] conversions n={n}", file=sys.stderr, flush=True)
+    ff = _ff()
+    x = _f64(n, 2100 + n % 1000)
+    got = ff.ff_from_f64(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    g = got.cpu().numpy()
+    hi, lo = oracle.from_f64(x)
+    assert same_bits(g[0], hi), mismatch_report(g[0], hi)
+    assert same_bits(g[1], lo), mismatch_report(g[1], lo)
+    pairs = fi.random_ff(n, 2200 + n % 1000, -100, 100, max_gap=40)
+    back = ff.ff_to_f64(pairs.cuda())
+    torch.cuda.synchronize()
+    want = oracle.to_f64(pairs[0].numpy(), pairs[1].numpy())
+    assert np.array_equal(back.cpu().numpy().view(np.uint64), want.view(np.uint64))
+
+
+def test_unaligned_planes_and_short_names():
+    ff = _ff()
+    n = 4099
+    x = _f64(n + 1, 2301)
+    xd = torch.from_numpy(x).cuda()[1:]                    # 8-byte aligned only
+    out = ff.ff_zeros((n + 1,), device="cuda")[:, 1:]       # 4-byte aligned planes
+    ff.from_float64(xd, out=out)
+    torch.cuda.synchronize()
+    hi, lo = oracle.from_f64(x[1:])
+    o = out.cpu().numpy()
+    assert same_bits(o[0], hi) and same_bits(o[1], lo)
+    back = torch.zeros(n + 1, dtype=torch.float64, device="cuda")[1:]
+    ff.to_float64(out, out=back)
+    torch.cuda.synchronize()
+    assert np.array_equal(back.cpu().numpy().view(np.uint64),
+                          oracle.to_f64(hi, lo).view(np.uint64))
+    a, b, _ = fi.mixed_ff_pair(1000, 2302, device="cuda")
+    assert torch.equal(ff.add(a, b), ff.ff_add(a, b))
+    assert torch.equal(ff.div(a, b), ff.ff_div(a, b))
