@@ -109,7 +109,14 @@ def _time_launches(fn, reps: int, stream, warmup: int = 1) -> float:
     return start.elapsed_time(end) / reps
 
 
-def secondary(stream) -> dict:
+def _oracle_timed(fn):
+    """Seconds of one call of an oracle function (single-threaded C)."""
+    t0 = time.perf_counter()
+    fn()
+    return time.perf_counter() - t0
+
+
+def secondary(stream, cpu: bool = True) -> dict:
     """The other float-float workloads, one line each (not part of the step)."""
     import torch
 
@@ -125,12 +132,27 @@ def secondary(stream) -> dict:
     a = fi.base_ff(n, 115001, device=dev)
     b = fi.base_ff(n, 115011, device=dev)
     r = ff.ff_empty((n,), device=dev)
-    # 1 GiB written between launches evicts the 25 MB working set from L2 and
-    # the 256 MB Infinity Cache; only the operator's own launch is timed
+    # cache-flushed: 1 GiB written between launches evicts the 25 MB working
+    # set from L2 and the 256 MB Infinity Cache; events bracket the operator's
+    # own launch, queued behind the fill so that no host gap is timed
     flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
     small = {}
     for name, fn in (("add", ff.ff_add), ("mul", ff.ff_mul)):
-        warm_ms = _time_launches(lambda: fn(a, b, out=r, stream=stream), 200, stream)
+        # cache-warm: 200 launches captured in one graph and replayed, so that
+        # the host's launch rate does not enter the time
+        fn(a, b, out=r, stream=stream)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(graph, stream=side):
+                cap = torch.cuda.current_stream(dev)
+                for _ in range(200):
+                    fn(a, b, out=r, stream=cap)
+        torch.cuda.synchronize()
+        warm_ms = min(_time_launches(graph.replay, 1, stream) for _ in range(3)) / 200
+        del graph
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(20)]
         for s_ev, e_ev in evs:
@@ -167,6 +189,14 @@ def secondary(stream) -> dict:
         ops = per_step * deg * n / (ms * 1e-3)
         horner[name] = {"ms": round(ms, 4), "Gpoints/s": round(n / (ms * 1e-3) / 1e9, 2),
                         "fp32_ops/s": ops, "alu_frac": round(ops / ALU_PEAK_OPS, 4)}
+    if cpu:
+        import oracle
+        m = 1 << 23
+        xs, cs = x[:m].cpu().numpy(), coef.cpu().numpy()
+        dt = _oracle_timed(lambda: oracle.horner_comp(cs, xs))
+        horner["cpu_baseline"] = {"value": m / dt, "unit": "points/s (compensated Horner)",
+                                  "cores": 1, "kind": "oracle",
+                                  "sample": f"first {m} points, single-threaded C oracle, {dt:.2f} s"}
     out["horner_2p26"] = horner
     del coef, x, y, yff
     torch.cuda.empty_cache()
@@ -189,6 +219,17 @@ def secondary(stream) -> dict:
                           "cfg": list(cfg),
                           "dot2_compensated": {"ms": round(ms2, 4), "GB/s": round(gbs2, 1),
                                                "hbm_frac": round(gbs2 / HBM_PEAK_GBS, 4)}}
+    if cpu:
+        import oracle
+        offs_h = offs.cpu().numpy()
+        nv = int((offs_h <= 150_000_000).sum()) - 1         # whole vectors, ~150 M elements
+        e = int(offs_h[nv])
+        xs, ys = x[:e].cpu().numpy(), y[:e].cpu().numpy()
+        dt = _oracle_timed(lambda: oracle.dot_seq_batched(xs, ys, offs_h[:nv + 1]))
+        out["dot_batched"]["cpu_baseline"] = {
+            "value": e / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {nv} vectors ({e} elements), sequential Add22 dot, "
+                      f"single-threaded C oracle, {dt:.2f} s"}
     del x, y, offs, res, ws
     torch.cuda.empty_cache()
 
@@ -210,6 +251,18 @@ def secondary(stream) -> dict:
         del wsg
     gemm["speedup_i8_vs_fma_loop"] = round(gemm["fma_loop"]["ms"] / gemm["sliced_i8"]["ms"], 1)
     gemm["speedup_bf16_vs_fma_loop"] = round(gemm["fma_loop"]["ms"] / gemm["sliced_bf16"]["ms"], 1)
+    if cpu:
+        import oracle
+        r = 192
+        Ah, Al = A[0, :r].cpu().numpy(), A[1, :r].cpu().numpy()
+        Bh, Bl = B[0, :, :r].contiguous().cpu().numpy(), B[1, :, :r].contiguous().cpu().numpy()
+        dt = _oracle_timed(lambda: oracle.gemm_ff_seq(Ah, Al, Bh, Bl))
+        rate = 2.0 * r * r * n / dt
+        gemm["cpu_baseline"] = {"value": rate / 1e12, "unit": "ff_TFLOP/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"{r} x {r} block of C at K = {n} (plain Add22/Mul22 "
+                                          f"loop, single-threaded C oracle, {dt:.2f} s; 4096^3 "
+                                          f"would take {flops / rate:.0f} s)"}
     out["gemm_4096"] = gemm
     del A, B, C
     torch.cuda.empty_cache()
@@ -229,6 +282,16 @@ def secondary(stream) -> dict:
                     "backward_GB/s": round(16 * m * m / (bwd * 1e-3) / 1e9, 1)}
     mv["backward_speedup_fast_vs_plain"] = round(mv["plain"]["backward_ms"] / mv["fast"]["backward_ms"], 1)
     mv["forward_speedup_fast_vs_plain"] = round(mv["plain"]["forward_ms"] / mv["fast"]["forward_ms"], 1)
+    if cpu:
+        import oracle
+        r = m
+        Ah, Al = A[0, :r].cpu().numpy(), A[1, :r].cpu().numpy()
+        xh, xl = xv[0].cpu().numpy().reshape(m, 1), xv[1].cpu().numpy().reshape(m, 1)
+        dt = _oracle_timed(lambda: oracle.gemm_ff_seq(Ah, Al, xh, xl))
+        mv["cpu_baseline"] = {"value": 8 * r * m / dt / 1e9, "unit": "forward GB/s of A",
+                              "cores": 1, "kind": "oracle",
+                              "sample": f"all {r} rows of y = A x (sequential Add22 of Mul22 "
+                                        f"terms, single-threaded C oracle, {dt:.2f} s)"}
     out["matvec_8192"] = mv
     del A, xv, g
     torch.cuda.empty_cache()
@@ -389,7 +452,7 @@ def main(argv=None) -> int:
     if not args.no_secondary:
         del a, b, r
         torch.cuda.empty_cache()
-        result["secondary"] = secondary(stream)
+        result["secondary"] = secondary(stream, cpu=not args.no_cpu_baseline)
     print(json.dumps(result), flush=True)
     return 0
 
