@@ -87,6 +87,9 @@ def parse_args(argv=None):
     p.add_argument("--cpu-seconds", type=float, default=12.0,
                    help="target duration of the CPU-baseline sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--dot-cfg", default=None,
+                   help="block,chunk,grid,unroll of the batched dot; skips the autotuner "
+                        "(so that a profile holds only launches of this shape)")
     p.add_argument("--no-secondary", action="store_true",
                    help="skip the batched-dot, GEMM and matvec measurements")
     return p.parse_args(argv)
@@ -116,7 +119,7 @@ def _oracle_timed(fn):
     return time.perf_counter() - t0
 
 
-def secondary(stream, cpu: bool = True) -> dict:
+def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
     """The other float-float workloads, one line each (not part of the step)."""
     import torch
 
@@ -204,7 +207,7 @@ def secondary(stream, cpu: bool = True) -> dict:
     log("[bench] batched dot: 4096 vectors, lengths floor(2^U[6,20])")
     x, y, offs = fi.batched_dot(115003, device=dev)
     total = x.numel()
-    cfg = autotune.dot_cfg(x, y, offs)
+    cfg = tuple(dot_cfg) if dot_cfg is not None else autotune.dot_cfg(x, y, offs)
     res = ff.ff_empty((offs.numel() - 1,), device=dev)
     ws = torch.empty(ff.ff_dot_batched_workspace_size(total, offs.numel() - 1, cfg),
                      dtype=torch.uint8, device=dev)
@@ -452,7 +455,12 @@ def main(argv=None) -> int:
     if not args.no_secondary:
         del a, b, r
         torch.cuda.empty_cache()
-        result["secondary"] = secondary(stream, cpu=not args.no_cpu_baseline)
+        dot_cfg = None
+        if args.dot_cfg:
+            dot_cfg = tuple(int(v) for v in args.dot_cfg.split(","))
+            if len(dot_cfg) != 4:
+                raise SystemExit("--dot-cfg takes four integers: block,chunk,grid,unroll")
+        result["secondary"] = secondary(stream, cpu=not args.no_cpu_baseline, dot_cfg=dot_cfg)
     print(json.dumps(result), flush=True)
     return 0
 
