@@ -82,6 +82,8 @@ _SIGS = {
     "oracle_dot2": ([_F, _F, _i64, _F], None),
     "oracle_sum2_batched": ([_F, _I64, _i64, _F], None),
     "oracle_dot2_batched": ([_F, _F, _I64, _i64, _F], None),
+    "oracle_dot_batched_backward": ([_F, _F, _I64, _i64, _i64, _F, _F, _F, _F, _F, _F, _F, _F],
+                                    None),
     "oracle_from_f64": ([_D, _F, _F, _i64], None),
     "oracle_to_f64": ([_F, _F, _D, _i64], None),
     "oracle_horner_f32": ([_F, _int, _F, _F, _i64], None),
@@ -288,6 +290,21 @@ def dot2_batched(x, y, offsets):
     out = np.empty(2 * (offs.size - 1), np.float32)
     lib().oracle_dot2_batched(_p(x), _p(y), _p(offs), offs.size - 1, _p(out))
     return out[0::2].copy(), out[1::2].copy()
+
+
+def dot_batched_backward(gh, gl, offsets, xh, xl, yh, yl):
+    """Gradients (dxh, dxl, dyh, dyl) of the batched float-float dot for
+    upstream gradients g_v = (gh[v], gl[v]): dx_i = Mul22(g_v, y_i),
+    dy_i = Mul22(g_v, x_i) for each element i of vector v, zero elsewhere."""
+    (gh, gl), nvec = _pair_inputs(gh, gl)
+    (xh, xl, yh, yl), n = _pair_inputs(xh, xl, yh, yl)
+    offs = np.ascontiguousarray(offsets, dtype=np.int64)
+    if offs.size != nvec + 1 or np.any(np.diff(offs) < 0) or offs[0] < 0 or offs[-1] > n:
+        raise ValueError("offsets: nvec + 1 non-decreasing values within [0, n]")
+    out = [np.empty(n, np.float32) for _ in range(4)]
+    lib().oracle_dot_batched_backward(_p(gh), _p(gl), _p(offs), nvec, n, _p(xh), _p(xl),
+                                      _p(yh), _p(yl), *(_p(o) for o in out))
+    return tuple(out)
 
 
 # --------------------------------------------------------------- conversions

@@ -577,6 +577,28 @@ void oracle_horner_ff(const float *ah, const float *al, int32_t degree,
     }
 }
 
+/* Backward pass of the batched float-float dot s_v = sum over vector v of
+ * x_i y_i, for upstream float-float gradients g_v: every element i of vector
+ * v gets dx_i = Mul22(g_v, y_i) and dy_i = Mul22(g_v, x_i) (FMA TwoProd);
+ * elements of no vector get zero gradients.  Offsets non-decreasing, within
+ * [0, total]. */
+void oracle_dot_batched_backward(const float *gh, const float *gl,
+                                 const int64_t *offsets, int64_t nvec,
+                                 int64_t total, const float *xh,
+                                 const float *xl, const float *yh,
+                                 const float *yl, float *dxh, float *dxl,
+                                 float *dyh, float *dyl)
+{
+    for (int64_t i = 0; i < total; ++i)
+        dxh[i] = dxl[i] = dyh[i] = dyl[i] = 0.0f;
+    for (int64_t v = 0; v < nvec; ++v) {
+        for (int64_t i = offsets[v]; i < offsets[v + 1]; ++i) {
+            mul22(gh[v], gl[v], yh[i], yl[i], 0, &dxh[i], &dxl[i]);
+            mul22(gh[v], gl[v], xh[i], xl[i], 0, &dyh[i], &dyl[i]);
+        }
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Exact accumulation: a long fixed-point accumulator                       */
 /* ------------------------------------------------------------------------ */

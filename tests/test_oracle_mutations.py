@@ -16,6 +16,7 @@ import test_oracle_accurate_add as ACC
 import test_oracle_accurate_mul_div as AMD
 import test_oracle_compensated as CMP
 import test_oracle_convert as CNV
+import test_oracle_dot_backward as DBW
 import test_oracle_horner as HOR
 import test_oracle_paper_tables as TAB
 import test_oracle_primitives as PRIM
@@ -86,6 +87,10 @@ CNV_PINS = [
     CNV.test_from_f64_of_binary32_values_is_exact,
     CNV.test_to_f64_rounds_once,
     CNV.test_round_trip_where_the_bits_fit,
+]
+DBW_PINS = [
+    DBW.test_power_of_two_gradients_are_exact_and_segment_correctly,
+    DBW.test_general_gradients_within_the_mul22_bound,
 ]
 CMP_PINS = [
     CMP.test_empty_and_single_terms,
@@ -158,6 +163,14 @@ MUTATIONS = [
      "        lo[i] = (float)x[i] - h;", CNV_PINS),
     ("to_f64_binary32_sum", "        x[i] = (double)hi[i] + (double)lo[i];",
      "        x[i] = (double)(hi[i] + lo[i]);", CNV_PINS),
+    ("dot_bwd_swapped_operands", "            mul22(gh[v], gl[v], yh[i], yl[i], 0, &dxh[i], &dxl[i]);",
+     "            mul22(gh[v], gl[v], xh[i], xl[i], 0, &dxh[i], &dxl[i]);", DBW_PINS),
+    ("dot_bwd_neighbour_gradient", "            mul22(gh[v], gl[v], xh[i], xl[i], 0, &dyh[i], &dyl[i]);",
+     "            mul22(gh[v > 0 ? v - 1 : v], gl[v], xh[i], xl[i], 0, &dyh[i], &dyl[i]);", DBW_PINS),
+    ("dot_bwd_dropped_low_word", "            mul22(gh[v], gl[v], yh[i], yl[i], 0, &dxh[i], &dxl[i]);",
+     "            mul22(gh[v], gl[v], yh[i], 0.0f, 0, &dxh[i], &dxl[i]);", DBW_PINS),
+    ("dot_bwd_no_zero_fill", "        dxh[i] = dxl[i] = dyh[i] = dyl[i] = 0.0f;",
+     "        dxh[i] = dxl[i] = dyh[i] = dyl[i] = 1.0f;", DBW_PINS),
     ("dot2_dropped_product_error", "        s = s + (q + r);", "        s = s + q;", CMP_PINS),
     ("dot2_dropped_sum_error", "        s = s + (q + r);", "        s = s + r;", CMP_PINS),
     ("sum2_dropped_error", "        s = s + q;\n    }\n    out2[0] = p;\n    out2[1] = s;\n}\n\nvoid oracle_dot2",
