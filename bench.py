@@ -217,11 +217,30 @@ def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
     ms2 = _time_launches(lambda: ff.ff_dot2_batched(x, y, offs, cfg=cfg, out=res, workspace=ws,
                                                     stream=stream), 10, stream)
     gbs2 = 8 * total / (ms2 * 1e-3) / 1e9
+    # backward for per-vector gradients: reads x and y (binary32), writes dx
+    # and dy (float-float): 24 bytes per element
+    gvec = torch.ones((2, offs.numel() - 1), device=dev)
+    gvec[1].zero_()
+    dxb, dyb = ff.ff_empty((total,), device=dev), ff.ff_empty((total,), device=dev)
+    gh, gl = gvec[0].data_ptr(), gvec[1].data_ptr()
+
+    def dot_bwd():
+        from paper_cs_0603115_amd import _lib
+        _lib.check("ff_dot_batched_backward", ff.lib.ff_dot_batched_backward(
+            gh, gl, offs.data_ptr(), offs.numel() - 1, total, x.data_ptr(), None, y.data_ptr(),
+            None, dxb[0].data_ptr(), dxb[1].data_ptr(), dyb[0].data_ptr(), dyb[1].data_ptr(),
+            stream.cuda_stream))
+    msb = _time_launches(dot_bwd, 10, stream)
+    gbsb = 24 * total / (msb * 1e-3) / 1e9
+    del dxb, dyb, gvec
     out["dot_batched"] = {"elements": total, "ms": round(ms, 4), "elements/s": total / (ms * 1e-3),
                           "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                           "cfg": list(cfg),
                           "dot2_compensated": {"ms": round(ms2, 4), "GB/s": round(gbs2, 1),
-                                               "hbm_frac": round(gbs2 / HBM_PEAK_GBS, 4)}}
+                                               "hbm_frac": round(gbs2 / HBM_PEAK_GBS, 4)},
+                          "backward": {"ms": round(msb, 4), "GB/s": round(gbsb, 1),
+                                       "hbm_frac": round(gbsb / HBM_PEAK_GBS, 4),
+                                       "bytes_per_element": 24}}
     if cpu:
         import oracle
         offs_h = offs.cpu().numpy()

@@ -336,6 +336,29 @@ ff_status ff_dot_backward(const float *g_hi, const float *g_lo,
                           float *dx_lo, float *dy_hi, float *dy_lo, int64_t n,
                           void *stream);
 
+/* Backward pass of the batched float-float dot (ff_dot_batched /
+ * ff_dot_ff_batched) for per-vector upstream gradients g_v (device, nvec
+ * float-float values g_hi[v] + g_lo[v]): every element i of vector v, i in
+ * [offsets[v], offsets[v+1]), gets
+ *   dx_i = Mul22(g_v, y_i),  dy_i = Mul22(g_v, x_i)   (FMA TwoProd),
+ * and every element of no vector (before offsets[0], from offsets[nvec] on)
+ * gets zero gradients, so all total_len entries of each output are written.
+ * x_lo / y_lo may be NULL (binary32 inputs, zero low words).  Either output
+ * pair may be NULL to skip it; x is read only for dy, y only for dx.
+ * offsets: device, nvec + 1 int64, non-decreasing within [0, total_len],
+ * as for the forward (violations give unspecified gradients, never accesses
+ * outside the arrays: offsets are clamped to [0, total_len]).
+ * Errors: FF_ERR_SIZE (nvec < 0, total_len < 0), FF_ERR_NULL, FF_ERR_ALIGN
+ * (offsets not 8-byte or a plane not 4-byte aligned), FF_ERR_HIP.
+ * total_len = 0 is a no-op. */
+ff_status ff_dot_batched_backward(const float *g_hi, const float *g_lo,
+                                  const int64_t *offsets, int32_t nvec,
+                                  int64_t total_len, const float *x_hi,
+                                  const float *x_lo, const float *y_hi,
+                                  const float *y_lo, float *dx_hi,
+                                  float *dx_lo, float *dy_hi, float *dy_lo,
+                                  void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Matrix product C = A B                                                   */
 /* ------------------------------------------------------------------------ */

@@ -27,7 +27,8 @@ __all__ = [
     "ff_horner_f32", "ff_horner_comp", "ff_horner_ff",
     "ff_dot_batched", "ff_dot_ff_batched", "ff_dot_batched_workspace_size",
     "ff_sum_batched", "ff_sum_ff_batched", "ff_dot2_batched", "ff_sum2_batched",
-    "ff_matvec", "ff_matvec_backward", "ff_dot_backward", "MATVEC_FAST", "MATVEC_PLAIN",
+    "ff_matvec", "ff_matvec_backward", "ff_dot_backward", "ff_dot_batched_backward",
+    "MATVEC_FAST", "MATVEC_PLAIN",
     "ff_gemm", "ff_gemm_workspace_size", "GEMM_FMA_LOOP", "GEMM_SLICED_BF16", "GEMM_SLICED_I8",
     "ff_empty", "ff_zeros", "ff_from_f64", "ff_to_f64",
     "add", "sub", "mul", "div", "dot_batched", "gemm", "matvec", "from_float64", "to_float64",
@@ -594,6 +595,47 @@ def ff_dot_backward(g: torch.Tensor, x: torch.Tensor, y: torch.Tensor, want_dx: 
     with torch.cuda.device(x.device):
         check("ff_dot_backward", lib.ff_dot_backward(gh, gl, xh, xl, yh, yl, dxh, dxl, dyh, dyl, n,
                                                      _stream_handle(stream)))
+    return dx, dy
+
+
+def _ff_or_f32_planes(t: torch.Tensor, name: str):
+    """(hi, lo or NULL, n) of a float-float (2, n) or binary32 (n,) vector."""
+    if isinstance(t, torch.Tensor) and t.dtype == torch.float32 and t.dim() == 1:
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name}: contiguous float32 vector on a HIP device expected")
+        return _ptr(t), _null(), t.numel()
+    _check_ff(t, name)
+    if t.dim() != 2:
+        raise ValueError(f"{name}: float-float vector (2, n) or binary32 vector (n,) expected")
+    hi, lo = _planes(t)
+    return hi, lo, t.shape[1]
+
+
+def ff_dot_batched_backward(g: torch.Tensor, x: torch.Tensor, y: torch.Tensor,
+                            offsets: torch.Tensor, want_dx: bool = True, want_dy: bool = True,
+                            stream=None):
+    """Backward pass of the batched dot for per-vector upstream gradients g
+    (2, nvec): every element i of vector v gets dx_i = g_v y_i and
+    dy_i = g_v x_i (Mul22), elements of no vector zeros.  x and y are
+    float-float (2, total) or binary32 (total,); the gradients are
+    float-float (2, total) (None when not wanted)."""
+    _check_ff(g, "g")
+    nvec = _check_offsets(offsets, g.device)
+    if g.dim() != 2 or g.shape[1] != nvec:
+        raise ValueError(f"g must have shape (2, {nvec})")
+    xh, xl, n = _ff_or_f32_planes(x, "x")
+    yh, yl, n2 = _ff_or_f32_planes(y, "y")
+    if n != n2 or x.device != g.device or y.device != g.device:
+        raise ValueError("x, y and g must agree in length and device")
+    dx = ff_empty((n,), device=g.device) if want_dx else None
+    dy = ff_empty((n,), device=g.device) if want_dy else None
+    gh, gl = _planes(g)
+    dxh, dxl = _planes(dx) if want_dx else (_null(), _null())
+    dyh, dyl = _planes(dy) if want_dy else (_null(), _null())
+    with torch.cuda.device(g.device):
+        check("ff_dot_batched_backward", lib.ff_dot_batched_backward(
+            gh, gl, ctypes.c_void_p(offsets.data_ptr()), nvec, n, xh, xl, yh, yl, dxh, dxl, dyh,
+            dyl, _stream_handle(stream)))
     return dx, dy
 
 

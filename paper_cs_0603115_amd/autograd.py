@@ -13,10 +13,10 @@ from __future__ import annotations
 
 import torch
 
-from . import (MATVEC_FAST, ff_dot_backward, ff_dot_ff_batched, ff_matvec,
-               ff_matvec_backward)
+from . import (MATVEC_FAST, ff_dot_backward, ff_dot_batched_backward, ff_dot_ff_batched,
+               ff_matvec, ff_matvec_backward)
 
-__all__ = ["FFMatVec", "FFDot", "ff_one"]
+__all__ = ["FFMatVec", "FFDot", "FFDotBatched", "ff_one"]
 
 
 def ff_one(device="cuda") -> torch.Tensor:
@@ -60,3 +60,22 @@ class FFDot(torch.autograd.Function):
         du, dv = ff_dot_backward(gs.contiguous(), u, v, want_dx=ctx.needs_input_grad[0],
                                  want_dy=ctx.needs_input_grad[1])
         return du, dv
+
+
+class FFDotBatched(torch.autograd.Function):
+    """s_v = sum over [offsets[v], offsets[v+1]) of x_i y_i for float-float
+    vectors x, y (2, total); s has shape (2, nvec).  Backward by
+    ff_dot_batched_backward: dx_i = g_v y_i, dy_i = g_v x_i."""
+
+    @staticmethod
+    def forward(ctx, x, y, offsets):
+        ctx.save_for_backward(x, y, offsets)
+        return ff_dot_ff_batched(x, y, offsets)
+
+    @staticmethod
+    def backward(ctx, gs):
+        x, y, offsets = ctx.saved_tensors
+        dx, dy = ff_dot_batched_backward(gs.contiguous(), x, y, offsets,
+                                         want_dx=ctx.needs_input_grad[0],
+                                         want_dy=ctx.needs_input_grad[1])
+        return dx, dy, None

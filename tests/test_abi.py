@@ -153,6 +153,25 @@ def test_conversion_validation(name):
     assert call(f64, f32[0] + 2, f32[1], 5) == ERR_ALIGN
 
 
+def test_dot_batched_backward_validation():
+    fn = ff.lib.ff_dot_batched_backward
+    g, o = (4096, 8192), 12288
+    xs, ys = (16384, 20480), (24576, 28672)
+    d = (32768, 36864, 40960, 45056)
+    call = lambda gg=g, off=o, nvec=3, total=100, x=xs, y=ys, out=d: fn(
+        gg[0], gg[1], off, nvec, total, x[0], x[1], y[0], y[1], *out, None)
+    assert call(nvec=-1) == ERR_SIZE
+    assert call(total=-1) == ERR_SIZE
+    assert call(total=0) == 0
+    assert call(out=(None, None, None, None)) == 0          # nothing wanted: no-op
+    assert call(out=(d[0], None, d[2], d[3])) == ERR_NULL   # half an output pair
+    assert call(off=None) == ERR_NULL
+    assert call(gg=(None, g[1])) == ERR_NULL
+    assert call(y=(None, ys[1])) == ERR_NULL                # dx needs y
+    assert call(off=o + 4) == ERR_ALIGN                     # offsets need 8 bytes
+    assert call(x=(xs[0] + 2, xs[1])) == ERR_ALIGN
+
+
 def test_copy_validation():
     assert ff.lib.ff_copy(4096, 8192, -3, None) == ERR_SIZE
     assert ff.lib.ff_copy(4096, 8192, 0, None) == 0

@@ -1,0 +1,164 @@
+"""GPU parity of the batched dot's backward pass (per-vector gradients
+through Mul22): every gradient word bit for bit against the oracle, and the
+autograd Function against an FP64 reference gradient and FP64 central
+differences of the bilinear loss L = sum_v w_v s_v.
+
+Cases: float-float and binary32 inputs (null low words), one output only,
+leading and trailing elements outside every vector, empty vectors, vectors
+shorter than a float4 group and longer than a wavefront's 8192-element
+slice, vector starts inside float4 groups, total lengths not a multiple of
+4, unaligned planes (the one-element path), no vectors at all, and the
+4096-vector batch of the benchmark (438 M elements) on sampled vectors.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import ff_inputs as fi
+import oracle
+from fpexact import mismatch_report, same_bits
+
+pytestmark = pytest.mark.gpu
+
+
+def _ff():
+    import paper_cs_0603115_amd as ff
+    return ff
+
+
+def _announce(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _offsets(lengths, lead=0):
+    return np.concatenate([[lead], lead + np.cumsum(lengths)]).astype(np.int64)
+
+
+def _check(got, want, label):
+    for k, (g, w) in enumerate(zip(got, want)):
+        assert same_bits(g, w), f"{label} word {k}:\n{mismatch_report(g, w)}"
+
+
+def _run(g, x, y, offs, want_dx=True, want_dy=True):
+    ff = _ff()
+    dx, dy = ff.ff_dot_batched_backward(g, x, y, offs, want_dx=want_dx, want_dy=want_dy)
+    torch.cuda.synchronize()
+    return (dx.cpu().numpy() if dx is not None else None,
+            dy.cpu().numpy() if dy is not None else None)
+
+
+def _planes(t):
+    t = t.cpu().numpy()
+    return (t[0], t[1]) if t.ndim == 2 else (t, np.zeros_like(t))
+
+
+CASES = {
+    "mixed": ([3, 1, 0, 5, 8190, 2, 9000, 0, 17, 4, 20000], 3, 11),
+    "tiny": ([1] * 300 + [2] * 100, 1, 2),
+    "one_long": ([50001], 0, 0),
+    "no_vectors": ([], 37, 0),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("inputs", ["ff", "f32"])
+def test_bitexact_against_oracle(case, inputs):
+    lengths, lead, trail = CASES[case]
+    _announce(f"[gpu] dot backward {case} ({inputs} inputs)")
+    offs = _offsets(lengths, lead)
+    total = int(offs[-1]) + trail
+    if inputs == "ff":
+        x, y = fi.random_ff(total, 5001, -20, 20), fi.random_ff(total, 5002, -20, 20)
+    else:
+        x, y = fi.random_f32(total, 5003, -20, 20), fi.random_f32(total, 5004, -20, 20)
+    g = fi.random_ff(len(lengths), 5005, -4, 4)
+    od = torch.from_numpy(offs).cuda()
+    dx, dy = _run(g.cuda(), x.cuda(), y.cuda(), od)
+    xh, xl = _planes(x)
+    yh, yl = _planes(y)
+    want = oracle.dot_batched_backward(g[0].numpy(), g[1].numpy(), offs, xh, xl, yh, yl)
+    _check(dx, want[:2], f"{case} dx")
+    _check(dy, want[2:], f"{case} dy")
+    # one output only
+    dx1, dy1 = _run(g.cuda(), x.cuda(), y.cuda(), od, want_dy=False)
+    assert dy1 is None
+    _check(dx1, want[:2], f"{case} dx alone")
+
+
+def test_unaligned_planes():
+    _announce("[gpu] dot backward, unaligned planes")
+    ff = _ff()
+    lengths = [5, 4099, 1, 3000]
+    offs = _offsets(lengths, 2)
+    total = int(offs[-1]) + 3
+    x = fi.random_ff(total + 1, 5011, -20, 20)
+    y = fi.random_ff(total + 1, 5012, -20, 20)
+    g = fi.random_ff(len(lengths), 5013, -4, 4)
+    xd, yd = x.cuda()[:, 1:], y.cuda()[:, 1:]        # 4-byte aligned planes only
+    dx, dy = ff.ff_dot_batched_backward(g.cuda(), xd, yd, torch.from_numpy(offs).cuda())
+    torch.cuda.synchronize()
+    want = oracle.dot_batched_backward(g[0].numpy(), g[1].numpy(), offs, x[0, 1:].numpy(),
+                                       x[1, 1:].numpy(), y[0, 1:].numpy(), y[1, 1:].numpy())
+    _check(dx.cpu().numpy(), want[:2], "dx")
+    _check(dy.cpu().numpy(), want[2:], "dy")
+
+
+def test_benchmark_batch_sampled():
+    # the 4096-vector batch (binary32 inputs) on the full arrays; compared
+    # on a few whole vectors from the start, middle and end
+    _announce("[gpu] dot backward on the 4096-vector batch")
+    x, y, offs = fi.batched_dot(115003, device="cuda")
+    nvec = offs.numel() - 1
+    g = fi.random_ff(nvec, 5021, -4, 4).cuda()
+    dx, dy = _ff().ff_dot_batched_backward(g, x, y, offs)
+    torch.cuda.synchronize()
+    oh = offs.cpu().numpy()
+    gn = g.cpu().numpy()
+    for v0, v1 in ((0, 3), (nvec // 2, nvec // 2 + 3), (nvec - 3, nvec)):
+        s, e = int(oh[v0]), int(oh[v1])
+        sub = oh[v0:v1 + 1] - s
+        xs, ys = x[s:e].cpu().numpy(), y[s:e].cpu().numpy()
+        z = np.zeros_like(xs)
+        want = oracle.dot_batched_backward(gn[0, v0:v1], gn[1, v0:v1], sub, xs, z, ys, z)
+        _check(dx[:, s:e].cpu().numpy(), want[:2], f"vectors {v0}..{v1} dx")
+        _check(dy[:, s:e].cpu().numpy(), want[2:], f"vectors {v0}..{v1} dy")
+    del x, y, dx, dy
+    torch.cuda.empty_cache()
+
+
+def test_autograd_against_fp64_gradient_and_finite_differences():
+    _announce("[gpu] FFDotBatched autograd")
+    from paper_cs_0603115_amd.autograd import FFDotBatched
+    lengths = [7, 300, 0, 1025, 64]
+    offs = _offsets(lengths)
+    total = int(offs[-1])
+    x = fi.gaussian_ff((total,), 5031).cuda().requires_grad_(True)
+    y = fi.gaussian_ff((total,), 5032).cuda().requires_grad_(True)
+    w = fi.gaussian_f32((len(lengths),), 5033)
+    od = torch.from_numpy(offs).cuda()
+    s = FFDotBatched.apply(x, y, od)
+    # L = sum_v w_v s_v: the upstream gradient of s_v is (w_v, 0)
+    s.backward(torch.stack([w, torch.zeros_like(w)]).cuda())
+    dx = x.grad.cpu().numpy().astype(np.float64)
+    dx = dx[0] + dx[1]
+    xv = x.detach().cpu().numpy().astype(np.float64)
+    yv = y.detach().cpu().numpy().astype(np.float64)
+    xv, yv = xv[0] + xv[1], yv[0] + yv[1]
+    owner = np.repeat(np.arange(len(lengths)), lengths)
+    ref = w.numpy().astype(np.float64)[owner] * yv
+    assert np.all(np.abs(dx - ref) <= 2.0 ** -43 * np.abs(ref) + 1e-300)
+
+    def loss(xx):
+        return sum(float(w[v]) * float(np.dot(xx[offs[v]:offs[v + 1]], yv[offs[v]:offs[v + 1]]))
+                   for v in range(len(lengths)))
+
+    rng = np.random.default_rng(5034)
+    for i in rng.choice(total, 32, replace=False):
+        h = 2.0 ** -12 * max(abs(xv[i]), 1.0)
+        xp, xm = xv.copy(), xv.copy()
+        xp[i] += h
+        xm[i] -= h
+        fd = (loss(xp) - loss(xm)) / (2 * h)
+        assert abs(fd - dx[i]) <= 1e-9 * max(1.0, abs(fd)), (i, fd, dx[i])

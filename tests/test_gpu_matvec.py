@@ -140,19 +140,23 @@ def test_backward_partial_requests_and_padded_rows():
     check_dA_bits(x, g, dA, "dA only")
 
 
-def test_dot_backward_elementwise():
+@pytest.mark.parametrize("n", [1, 4095, 4097, 100003])
+def test_dot_backward_elementwise(n):
     ff = _ff()
-    n = 100003
     u = fi.gaussian_ff((n,), 41).cuda()
     v = fi.gaussian_ff((n,), 42).cuda()
     g = fi.gaussian_ff((1,), 43).cuda()
-    du, dv = ff.ff_dot_backward(g, u, v)
     un, vn, gn = u.cpu().numpy(), v.cpu().numpy(), g.cpu().numpy()
     gh, gl = np.full(n, gn[0, 0], np.float32), np.full(n, gn[1, 0], np.float32)
-    for got, other in ((du, vn), (dv, un)):
-        rh, rl = oracle.mul22(gh, gl, other[0], other[1])
-        got = got.cpu().numpy()
-        assert same_bits(got[0], rh) and same_bits(got[1], rl)
+    for want_dx, want_dy in ((True, True), (True, False), (False, True)):
+        du, dv = ff.ff_dot_backward(g, u, v, want_dx=want_dx, want_dy=want_dy)
+        for got, other, wanted in ((du, vn, want_dx), (dv, un, want_dy)):
+            assert (got is not None) == wanted
+            if got is None:
+                continue
+            rh, rl = oracle.mul22(gh, gl, other[0], other[1])
+            got = got.cpu().numpy()
+            assert same_bits(got[0], rh) and same_bits(got[1], rl)
 
 
 def test_autograd_matvec_then_dot():
