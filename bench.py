@@ -404,8 +404,9 @@ def main(argv=None) -> int:
 
     kernel_ms = {op: sum(s.elapsed_time(e) for s, e in events[op]) / args.steps for op in OPS}
 
-    # Bandwidth reference: the ff_copy probe (one plane in, one out, same
-    # 16-byte non-temporal pattern) over N binary32 words, after the timed
+    # Bandwidth reference: the ff_copy probe (one plane in, one out; one
+    # float4 group per lane, 16-byte non-temporal loads and stores, the
+    # fastest copy pattern measured) over N binary32 words, after the timed
     # region.  It also calibrates the HBM byte counters.
     copy_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(args.steps)]

@@ -4,21 +4,22 @@
 //
 // Layout: four input planes and two output planes of n binary32 words.
 // Each operator reads 16 bytes and writes 8 bytes per element and performs
-// at most ~45 VALU operations, far below the gfx950 ridge point (~118 lane
-// operations per 24 bytes at 8 TB/s), so the kernels are HBM-bound.  The
-// fast path streams the planes with 16-byte non-temporal loads and stores:
-// every thread owns kUnroll float4 groups of each plane, the groups of a
-// workgroup are contiguous, and consecutive lanes touch consecutive 16-byte
-// words so that each wavefront instruction moves 1 KiB per plane.
+// at most ~45 VALU operations, far below the gfx950 ridge point (~236
+// binary32 operations per 24 bytes at 8 TB/s), so the kernels are
+// HBM-bound.  One workgroup of kBlock threads per block of kBlock * kPer
+// consecutive elements, in launch order; thread t takes elements
+// b0 + t + kBlock k (k < kPer) of every plane, so each wavefront access is
+// 256 contiguous bytes of a plane, issues all its non-temporal 4-byte loads
+// before any arithmetic, and stores non-temporally.  Any 4-byte alignment.
+// Below 2^22 elements (cache-resident) one float4 group per plane and thread
+// instead, when the planes are 16-byte aligned.
 #include "ff_device.h"
 #include "ff_host.h"
 
 namespace ffk {
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
 // Operator tags: kernels are templated on these so that profiles name the
-// operator (e.g. ffk::ew_vec<ffk::Add22>).
+// operator (e.g. ffk::ew_stream<ffk::Add22>).
 struct Add22 { static constexpr int op = ffd::OP_ADD; };
 struct Sub22 { static constexpr int op = ffd::OP_SUB; };
 struct Mul22 { static constexpr int op = ffd::OP_MUL; };
@@ -29,36 +30,61 @@ struct Sub22Accurate { static constexpr int op = ffd::OP_SUB_ACCURATE; };
 struct Mul22Accurate { static constexpr int op = ffd::OP_MUL_ACCURATE; };
 struct Div22Accurate { static constexpr int op = ffd::OP_DIV_ACCURATE; };
 
-// Launch shape chosen by a sweep on MI355X over workgroup sizes 256-1024,
-// 1-8 float4 groups per thread, persistent grids, XCD-contiguous tile
-// orders and plane base offsets: 1024 threads with one float4 group per
-// plane per thread reached 6.1 TB/s for every operator (the plain copy probe
-// of the same pattern: 6.3 TB/s).
+// Launch shape chosen by sweeps on MI355X at N = 2^28 (Add22, Mul22,
+// Div22): kBlock 256-1024 threads by 1-32 elements per thread of 4-byte
+// lane-contiguous accesses, against one float4 group per plane per lane
+// (2-8 groups, persistent grids, XCD-contiguous orders and plane offsets
+// before that).  1024 threads by 2 elements moved 6.3-6.4 TB/s; the best
+// float4 form 5.8-5.95 TB/s.
 constexpr int kBlock = 1024;  // 16 wavefronts of 64 lanes
-constexpr int kUnroll = 1;    // float4 groups per thread per plane
+constexpr int kPer = 2;       // elements per thread per plane
+constexpr int64_t kSpan = static_cast<int64_t>(kBlock) * kPer;
 
 template <typename T>
 __device__ __forceinline__ T ld_nt(const T *p) { return __builtin_nontemporal_load(p); }
 template <typename T>
 __device__ __forceinline__ void st_nt(T v, T *p) { __builtin_nontemporal_store(v, p); }
 
-template <int OP>
-__device__ __forceinline__ void apply4(const f32x4 &ah, const f32x4 &al, const f32x4 &bh,
-                                       const f32x4 &bl, f32x4 &rh, f32x4 &rl)
+template <class Tag>
+__global__ __launch_bounds__(kBlock) void ew_stream(const float *__restrict__ ah,
+                                                      const float *__restrict__ al,
+                                                      const float *__restrict__ bh,
+                                                      const float *__restrict__ bl,
+                                                      float *__restrict__ rh,
+                                                      float *__restrict__ rl, int64_t n)
 {
+    const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kSpan + threadIdx.x;
+    float xah[kPer], xal[kPer], xbh[kPer], xbl[kPer];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        float h, l;
-        ffd::apply<OP>(ah[k], al[k], bh[k], bl[k], h, l);
-        rh[k] = h;
-        rl[k] = l;
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t i = b0 + static_cast<int64_t>(kBlock) * k;
+        const bool in = i < n;
+        xah[k] = in ? ld_nt(ah + i) : 0.0f;
+        xal[k] = in ? ld_nt(al + i) : 0.0f;
+        xbh[k] = in ? ld_nt(bh + i) : 0.0f;
+        xbl[k] = in ? ld_nt(bl + i) : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t i = b0 + static_cast<int64_t>(kBlock) * k;
+        if (i < n) {
+            float h, l;
+            ffd::apply<Tag::op>(xah[k], xal[k], xbh[k], xbl[k], h, l);
+            st_nt(h, rh + i);
+            st_nt(l, rl + i);
+        }
     }
 }
 
-// Vector path: planes 16-byte aligned; element groups [0, nvec) of 4 floats.
-// Workgroup w owns groups [w*kBlock*kUnroll, (w+1)*kBlock*kUnroll); lane t
-// of the workgroup takes groups t, t + kBlock, ... so each load instruction
-// of a wavefront is one contiguous 1 KiB segment.
+// Below kSmallN elements the data sit in the 256 MB Infinity Cache and the
+// launches are latency-bound; there one float4 group of every plane per
+// thread (four times fewer load instructions) is as fast or faster (Add22 at
+// 2^21: 7.6 against 8.6 us), while the lane-contiguous form wins from 2^22
+// on (16.5 against 17.2 us).  The tail of n that is not a whole float4
+// group runs in the lane-contiguous kernel.
+constexpr int64_t kSmallN = int64_t(1) << 22;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 template <class Tag>
 __global__ __launch_bounds__(kBlock) void ew_vec(const f32x4 *__restrict__ ah,
                                                    const f32x4 *__restrict__ al,
@@ -67,67 +93,34 @@ __global__ __launch_bounds__(kBlock) void ew_vec(const f32x4 *__restrict__ ah,
                                                    f32x4 *__restrict__ rh,
                                                    f32x4 *__restrict__ rl, int64_t nvec)
 {
-    const int64_t first = static_cast<int64_t>(blockIdx.x) * (kBlock * kUnroll) + threadIdx.x;
-    f32x4 xah[kUnroll], xal[kUnroll], xbh[kUnroll], xbl[kUnroll];
-    if (static_cast<int64_t>(blockIdx.x + 1) * (kBlock * kUnroll) <= nvec) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= nvec)
+        return;
+    const f32x4 xah = ld_nt(ah + i), xal = ld_nt(al + i), xbh = ld_nt(bh + i),
+                xbl = ld_nt(bl + i);
+    f32x4 oh, ol;
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int64_t i = first + u * kBlock;
-            xah[u] = ld_nt(ah + i);
-            xal[u] = ld_nt(al + i);
-            xbh[u] = ld_nt(bh + i);
-            xbl[u] = ld_nt(bl + i);
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int64_t i = first + u * kBlock;
-            f32x4 oh, ol;
-            apply4<Tag::op>(xah[u], xal[u], xbh[u], xbl[u], oh, ol);
-            st_nt(oh, rh + i);
-            st_nt(ol, rl + i);
-        }
-    } else {
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int64_t i = first + u * kBlock;
-            if (i < nvec) {
-                f32x4 oh, ol;
-                apply4<Tag::op>(ld_nt(ah + i), ld_nt(al + i), ld_nt(bh + i), ld_nt(bl + i), oh, ol);
-                st_nt(oh, rh + i);
-                st_nt(ol, rl + i);
-            }
-        }
+    for (int k = 0; k < 4; ++k) {
+        float h, l;
+        ffd::apply<Tag::op>(xah[k], xal[k], xbh[k], xbl[k], h, l);
+        oh[k] = h;
+        ol[k] = l;
     }
+    st_nt(oh, rh + i);
+    st_nt(ol, rl + i);
 }
 
-// Scalar path: any 4-byte alignment, grid-stride over [0, n).
-template <class Tag>
-__global__ __launch_bounds__(kBlock) void ew_scalar(const float *__restrict__ ah,
-                                                      const float *__restrict__ al,
-                                                      const float *__restrict__ bh,
-                                                      const float *__restrict__ bl,
-                                                      float *__restrict__ rh,
-                                                      float *__restrict__ rl, int64_t n)
-{
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
-        float h, l;
-        ffd::apply<Tag::op>(ah[i], al[i], bh[i], bl[i], h, l);
-        rh[i] = h;
-        rl[i] = l;
-    }
-}
+// The copy probe (bandwidth reference and counter calibration): one plane
+// in, one out, one float4 group per lane with 16-byte non-temporal loads and
+// stores -- for a plain copy the fastest pattern measured (6.3 TB/s; the
+// lane-contiguous 4-byte form of ew_stream copies at 5.7).
 
 __global__ __launch_bounds__(kBlock) void copy_vec(const f32x4 *__restrict__ src,
                                                      f32x4 *__restrict__ dst, int64_t nvec)
 {
-    const int64_t first = static_cast<int64_t>(blockIdx.x) * (kBlock * kUnroll) + threadIdx.x;
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-        const int64_t i = first + u * kBlock;
-        if (i < nvec)
-            st_nt(ld_nt(src + i), dst + i);
-    }
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < nvec)
+        st_nt(ld_nt(src + i), dst + i);
 }
 
 __global__ __launch_bounds__(kBlock) void copy_scalar(const float *__restrict__ src,
@@ -136,12 +129,6 @@ __global__ __launch_bounds__(kBlock) void copy_scalar(const float *__restrict__ 
     const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride)
         dst[i] = src[i];
-}
-
-int scalar_grid(int64_t n)
-{
-    const int64_t blocks = ffh::cdiv(n, kBlock);
-    return static_cast<int>(blocks < 65536 ? blocks : 65536);
 }
 
 template <class Tag>
@@ -155,34 +142,32 @@ ff_status elementwise(const float *ah, const float *al, const float *bh, const f
     if (!ah || !al || !bh || !bl || !rh || !rl)
         return FF_ERR_NULL;
     const void *ptrs[6] = {ah, al, bh, bl, rh, rl};
-    bool vec = true;
-    for (const void *p : ptrs) {
+    for (const void *p : ptrs)
         if (!ffh::aligned(p, 4))
             return FF_ERR_ALIGN;
-        vec = vec && ffh::aligned(p, 16);
-    }
     hipStream_t stream = ffh::as_stream(stream_ptr);
+    bool vec = n < kSmallN;
+    for (const void *p : ptrs)
+        vec = vec && ffh::aligned(p, 16);
+    int64_t done = 0;
     if (vec) {
         const int64_t nvec = n / 4;
-        const int64_t done = nvec * 4;
-        if (nvec > 0) {
-            const int64_t blocks = ffh::cdiv(nvec, kBlock * kUnroll);
-            if (blocks > INT32_MAX)
-                return FF_ERR_SIZE;
-            hipLaunchKernelGGL(ew_vec<Tag>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0,
-                               stream, reinterpret_cast<const f32x4 *>(ah),
+        done = 4 * nvec;
+        if (nvec > 0)
+            hipLaunchKernelGGL(ew_vec<Tag>, dim3(static_cast<unsigned>(ffh::cdiv(nvec, kBlock))),
+                               dim3(kBlock), 0, stream, reinterpret_cast<const f32x4 *>(ah),
                                reinterpret_cast<const f32x4 *>(al),
                                reinterpret_cast<const f32x4 *>(bh),
-                               reinterpret_cast<const f32x4 *>(bl),
-                               reinterpret_cast<f32x4 *>(rh), reinterpret_cast<f32x4 *>(rl),
-                               nvec);
-        }
-        if (done < n)
-            hipLaunchKernelGGL(ew_scalar<Tag>, dim3(1), dim3(kBlock), 0, stream, ah + done,
-                               al + done, bh + done, bl + done, rh + done, rl + done, n - done);
-    } else {
-        hipLaunchKernelGGL(ew_scalar<Tag>, dim3(scalar_grid(n)), dim3(kBlock), 0, stream, ah, al,
-                           bh, bl, rh, rl, n);
+                               reinterpret_cast<const f32x4 *>(bl), reinterpret_cast<f32x4 *>(rh),
+                               reinterpret_cast<f32x4 *>(rl), nvec);
+    }
+    if (done < n) {
+        const int64_t blocks = ffh::cdiv(n - done, kSpan);
+        if (blocks > INT32_MAX)
+            return FF_ERR_SIZE;
+        hipLaunchKernelGGL(ew_stream<Tag>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0,
+                           stream, ah + done, al + done, bh + done, bl + done, rh + done,
+                           rl + done, n - done);
     }
     return ffh::launch_status();
 }
@@ -258,22 +243,23 @@ ff_status ff_copy(const float *src, float *dst, int64_t n, void *stream_ptr)
     if (!ffh::aligned(src, 4) || !ffh::aligned(dst, 4))
         return FF_ERR_ALIGN;
     hipStream_t stream = ffh::as_stream(stream_ptr);
+    int64_t done = 0;
     if (ffh::aligned(src, 16) && ffh::aligned(dst, 16)) {
-        const int64_t nvec = n / 4, done = nvec * 4;
+        const int64_t nvec = n / 4;
+        done = nvec * 4;
         if (nvec > 0) {
-            const int64_t blocks = ffh::cdiv(nvec, kBlock * kUnroll);
+            const int64_t blocks = ffh::cdiv(nvec, kBlock);
             if (blocks > INT32_MAX)
                 return FF_ERR_SIZE;
             hipLaunchKernelGGL(copy_vec, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0,
                                stream, reinterpret_cast<const f32x4 *>(src),
                                reinterpret_cast<f32x4 *>(dst), nvec);
         }
-        if (done < n)
-            hipLaunchKernelGGL(copy_scalar, dim3(1), dim3(kBlock), 0, stream, src + done,
-                               dst + done, n - done);
-    } else {
-        hipLaunchKernelGGL(copy_scalar, dim3(scalar_grid(n)), dim3(kBlock), 0, stream, src, dst,
-                           n);
+    }
+    if (done < n) {
+        const int64_t blocks = ffh::cdiv(n - done, kBlock);
+        hipLaunchKernelGGL(copy_scalar, dim3(static_cast<unsigned>(blocks < 65536 ? blocks : 65536)),
+                           dim3(kBlock), 0, stream, src + done, dst + done, n - done);
     }
     return ffh::launch_status();
 }

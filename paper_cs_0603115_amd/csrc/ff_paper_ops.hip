@@ -6,16 +6,15 @@
 //   binary32 add, multiply and multiply-add (one rounding).
 //
 // Same streaming structure as the float-float operators: 1024-thread
-// workgroups, one float4 group of every plane per thread, non-temporal
-// 16-byte loads and stores, a scalar kernel for the tail and for planes that
-// are not 16-byte aligned.  Bytes per element: 12 (add, mul), 16 (mad, Add12,
+// workgroups in launch order, two lane-contiguous elements per thread and
+// plane, all 4-byte non-temporal loads issued before the arithmetic, any
+// 4-byte alignment; one float4 group per plane and thread below 2^22
+// elements.  Bytes per element: 12 (add, mul), 16 (mad, Add12,
 // Mul12); all HBM-bound at large n, launch-bound at the paper's sizes.
 #include "ff_device.h"
 #include "ff_host.h"
 
 namespace ffk {
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kStreamBlock = 1024;
 
@@ -63,6 +62,14 @@ struct StreamPlanes {
     float *out[OUT];
 };
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Below kStreamSmallN elements (cache-resident, latency-bound launches) one
+// float4 group of every plane per thread is faster, as for the float-float
+// operators; the tail that is not a whole group and larger n run the
+// lane-contiguous kernel.
+constexpr int64_t kStreamSmallN = int64_t(1) << 22;
+
 template <class Op>
 __global__ __launch_bounds__(kStreamBlock) void stream_vec(StreamPlanes<Op::kIn, Op::kOut> p,
                                                            int64_t nvec)
@@ -90,21 +97,32 @@ __global__ __launch_bounds__(kStreamBlock) void stream_vec(StreamPlanes<Op::kIn,
         __builtin_nontemporal_store(y[k], reinterpret_cast<f32x4 *>(p.out[k]) + g);
 }
 
+constexpr int kStreamPer = 2;   // elements.per thread per plane
+constexpr int64_t kStreamSpan = static_cast<int64_t>(kStreamBlock) * kStreamPer;
+
 template <class Op>
-__global__ __launch_bounds__(kStreamBlock) void stream_scalar(StreamPlanes<Op::kIn, Op::kOut> p,
-                                                              int64_t n)
+__global__ __launch_bounds__(kStreamBlock) void stream_op_kernel(StreamPlanes<Op::kIn, Op::kOut> p,
+                                                                 int64_t n)
 {
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * kStreamBlock;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kStreamBlock + threadIdx.x; i < n;
-         i += stride) {
-        float xi[Op::kIn], yo[Op::kOut];
+    const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kStreamSpan + threadIdx.x;
+    float x[kStreamPer][Op::kIn];
 #pragma unroll
-        for (int k = 0; k < Op::kIn; ++k)
-            xi[k] = p.in[k][i];
-        Op::apply(xi, yo);
+    for (int k = 0; k < kStreamPer; ++k) {
+        const int64_t i = b0 + static_cast<int64_t>(kStreamBlock) * k;
 #pragma unroll
-        for (int k = 0; k < Op::kOut; ++k)
-            p.out[k][i] = yo[k];
+        for (int q = 0; q < Op::kIn; ++q)
+            x[k][q] = i < n ? __builtin_nontemporal_load(p.in[q] + i) : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < kStreamPer; ++k) {
+        const int64_t i = b0 + static_cast<int64_t>(kStreamBlock) * k;
+        if (i < n) {
+            float y[Op::kOut];
+            Op::apply(x[k], y);
+#pragma unroll
+            for (int q = 0; q < Op::kOut; ++q)
+                __builtin_nontemporal_store(y[q], p.out[q] + i);
+        }
     }
 }
 
@@ -115,33 +133,32 @@ ff_status stream_op(StreamPlanes<Op::kIn, Op::kOut> p, int64_t n, void *stream_p
         return FF_ERR_SIZE;
     if (n == 0)
         return FF_OK;
-    bool vec = true;
     for (int k = 0; k < Op::kIn; ++k) {
         if (!p.in[k])
             return FF_ERR_NULL;
         if (!ffh::aligned(p.in[k], 4))
             return FF_ERR_ALIGN;
-        vec = vec && ffh::aligned(p.in[k], 16);
     }
     for (int k = 0; k < Op::kOut; ++k) {
         if (!p.out[k])
             return FF_ERR_NULL;
         if (!ffh::aligned(p.out[k], 4))
             return FF_ERR_ALIGN;
-        vec = vec && ffh::aligned(p.out[k], 16);
     }
     hipStream_t st = ffh::as_stream(stream_ptr);
+    bool vec = n < kStreamSmallN;
+    for (int k = 0; k < Op::kIn; ++k)
+        vec = vec && ffh::aligned(p.in[k], 16);
+    for (int k = 0; k < Op::kOut; ++k)
+        vec = vec && ffh::aligned(p.out[k], 16);
     int64_t done = 0;
     if (vec) {
         const int64_t nvec = n / 4;
         done = 4 * nvec;
-        if (nvec > 0) {
-            const int64_t blocks = ffh::cdiv(nvec, kStreamBlock);
-            if (blocks > INT32_MAX)
-                return FF_ERR_SIZE;
-            hipLaunchKernelGGL(stream_vec<Op>, dim3(static_cast<unsigned>(blocks)),
+        if (nvec > 0)
+            hipLaunchKernelGGL(stream_vec<Op>,
+                               dim3(static_cast<unsigned>(ffh::cdiv(nvec, kStreamBlock))),
                                dim3(kStreamBlock), 0, st, p, nvec);
-        }
     }
     if (done < n) {
         StreamPlanes<Op::kIn, Op::kOut> rest = p;
@@ -149,9 +166,10 @@ ff_status stream_op(StreamPlanes<Op::kIn, Op::kOut> p, int64_t n, void *stream_p
             rest.in[k] += done;
         for (int k = 0; k < Op::kOut; ++k)
             rest.out[k] += done;
-        const int64_t blocks = ffh::cdiv(n - done, kStreamBlock);
-        hipLaunchKernelGGL(stream_scalar<Op>,
-                           dim3(static_cast<unsigned>(blocks < 65536 ? blocks : 65536)),
+        const int64_t blocks = ffh::cdiv(n - done, kStreamSpan);
+        if (blocks > INT32_MAX)
+            return FF_ERR_SIZE;
+        hipLaunchKernelGGL(stream_op_kernel<Op>, dim3(static_cast<unsigned>(blocks)),
                            dim3(kStreamBlock), 0, st, rest, n - done);
     }
     return ffh::launch_status();
