@@ -109,6 +109,41 @@ def test_in_place_output(op):
     assert_parity(op, a_copy, b, a, "in-place")
 
 
+def _special_pairs(tile):
+    """Every pair of special high words (signed zeros, +-1, +-inf, NaN, the
+    largest finite, the smallest normal, a subnormal, 3), each with a zero
+    and a small low word, tiled to reach the requested size."""
+    f32 = np.float32
+    hi = np.array([0.0, -0.0, 1.0, -1.0, np.inf, -np.inf, np.nan, np.finfo(f32).max,
+                   -np.finfo(f32).max, np.finfo(f32).tiny, 1e-40, 3.0], dtype=f32)
+    lo_of = lambda h: np.where(np.isfinite(h) & (np.abs(h) >= f32(2.0 ** -100)),
+                               (h * f32(2.0 ** -30)).astype(f32), f32(0.0))
+    ah, bh = np.meshgrid(hi, hi, indexing="ij")
+    ah, bh = ah.ravel(), bh.ravel()
+    al_small, bl_small = lo_of(ah), lo_of(bh)
+    z = np.zeros_like(ah)
+    a = np.concatenate([np.stack([ah, z]), np.stack([ah, al_small]), np.stack([ah, z]),
+                        np.stack([ah, al_small])], axis=1)
+    b = np.concatenate([np.stack([bh, z]), np.stack([bh, z]), np.stack([bh, bl_small]),
+                        np.stack([bh, bl_small])], axis=1)
+    reps = -(-tile // a.shape[1])
+    return (torch.from_numpy(np.tile(a, (1, reps))[:, :tile].copy()),
+            torch.from_numpy(np.tile(b, (1, reps))[:, :tile].copy()))
+
+
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("n", [576, (1 << 22) + 3])
+def test_special_values_match_the_oracle(op, n):
+    # the paper excludes NaN, infinities and overflow from its inputs; the
+    # kernels still follow the oracle through them (IEEE propagation along
+    # the same operation sequences; any NaN equals any NaN).  n covers the
+    # float4 form (below 2^22) and the lane-contiguous form.
+    _announce(f"[gpu] elementwise special values op={op} n={n}")
+    a, b = _special_pairs(n)
+    a, b = a.cuda(), b.cuda()
+    assert_parity(op, a, b, gpu_op(op, a, b), f"specials n={n}")
+
+
 def test_zero_length_is_a_noop():
     a = torch.empty(2, 0, device="cuda")
     r = gpu_op("add", a, a)
