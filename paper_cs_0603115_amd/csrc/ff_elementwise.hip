@@ -35,7 +35,8 @@ struct Div22Accurate { static constexpr int op = ffd::OP_DIV_ACCURATE; };
 // lane-contiguous accesses, against one float4 group per plane per lane
 // (2-8 groups, persistent grids, XCD-contiguous orders and plane offsets
 // before that).  1024 threads by 2 elements moved 6.3-6.4 TB/s; the best
-// float4 form 5.8-5.95 TB/s.
+// float4 form 5.8-5.95 TB/s.  Issuing the loads plane by plane added
+// another 1-1.5 % (6.31-6.36 TB/s).
 constexpr int kBlock = 1024;  // 16 wavefronts of 64 lanes
 constexpr int kPer = 2;       // elements per thread per plane
 constexpr int64_t kSpan = static_cast<int64_t>(kBlock) * kPer;
@@ -44,6 +45,18 @@ template <typename T>
 __device__ __forceinline__ T ld_nt(const T *p) { return __builtin_nontemporal_load(p); }
 template <typename T>
 __device__ __forceinline__ void st_nt(T v, T *p) { __builtin_nontemporal_store(v, p); }
+
+// The kPer lane-contiguous elements b0 + kBlock * k of one plane; zero
+// past n.
+__device__ __forceinline__ void load_plane(const float *__restrict__ p, int64_t b0, int64_t n,
+                                           float (&v)[kPer])
+{
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int64_t i = b0 + static_cast<int64_t>(kBlock) * k;
+        v[k] = i < n ? ld_nt(p + i) : 0.0f;
+    }
+}
 
 template <class Tag>
 __global__ __launch_bounds__(kBlock) void ew_stream(const float *__restrict__ ah,
@@ -55,15 +68,13 @@ __global__ __launch_bounds__(kBlock) void ew_stream(const float *__restrict__ ah
 {
     const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kSpan + threadIdx.x;
     float xah[kPer], xal[kPer], xbh[kPer], xbl[kPer];
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        const int64_t i = b0 + static_cast<int64_t>(kBlock) * k;
-        const bool in = i < n;
-        xah[k] = in ? ld_nt(ah + i) : 0.0f;
-        xal[k] = in ? ld_nt(al + i) : 0.0f;
-        xbh[k] = in ? ld_nt(bh + i) : 0.0f;
-        xbl[k] = in ? ld_nt(bl + i) : 0.0f;
-    }
+    // All loads are issued before any arithmetic, one plane at a time
+    // (a.hi, b.hi, a.lo, b.lo): plane by plane measured 1-1.5 % faster than
+    // element by element at N = 2^28.
+    load_plane(ah, b0, n, xah);
+    load_plane(bh, b0, n, xbh);
+    load_plane(al, b0, n, xal);
+    load_plane(bl, b0, n, xbl);
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int64_t i = b0 + static_cast<int64_t>(kBlock) * k;

@@ -106,12 +106,27 @@ __global__ __launch_bounds__(kStreamBlock) void stream_op_kernel(StreamPlanes<Op
 {
     const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kStreamSpan + threadIdx.x;
     float x[kStreamPer][Op::kIn];
+    // Every load is issued before any arithmetic.  Measured at N = 2^26 and
+    // 2^28: with two output planes, issuing the loads one input plane at a
+    // time is 1 % faster than element by element; with one output plane it
+    // is 3-5 % slower, so those kernels keep the element order.
+    if constexpr (Op::kOut >= 2) {
 #pragma unroll
-    for (int k = 0; k < kStreamPer; ++k) {
-        const int64_t i = b0 + static_cast<int64_t>(kStreamBlock) * k;
+        for (int q = 0; q < Op::kIn; ++q) {
 #pragma unroll
-        for (int q = 0; q < Op::kIn; ++q)
-            x[k][q] = i < n ? __builtin_nontemporal_load(p.in[q] + i) : 0.0f;
+            for (int k = 0; k < kStreamPer; ++k) {
+                const int64_t i = b0 + static_cast<int64_t>(kStreamBlock) * k;
+                x[k][q] = i < n ? __builtin_nontemporal_load(p.in[q] + i) : 0.0f;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kStreamPer; ++k) {
+            const int64_t i = b0 + static_cast<int64_t>(kStreamBlock) * k;
+#pragma unroll
+            for (int q = 0; q < Op::kIn; ++q)
+                x[k][q] = i < n ? __builtin_nontemporal_load(p.in[q] + i) : 0.0f;
+        }
     }
 #pragma unroll
     for (int k = 0; k < kStreamPer; ++k) {
