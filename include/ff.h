@@ -24,7 +24,8 @@
  *           propagate as IEEE arithmetic makes them, and division by zero
  *           gives IEEE infinities/NaN (not a meaningful float-float value).
  * Alignment Float pointers must be 4-byte aligned (FF_ERR_ALIGN otherwise).
- *           16-byte aligned planes take the vectorised fast path.
+ *           Where an entry point has a float4 path for 16-byte aligned
+ *           planes, its comment says when that path runs.
  * Aliasing  An output plane may be the same array as an input plane (in-place
  *           operation); partially overlapping arrays are undefined.
  * Numerics  Device code is compiled with contraction off, binary32 denormals
@@ -74,9 +75,12 @@ const char *ff_last_error(void);
 /* ------------------------------------------------------------------------ */
 /* Elementwise operators on n float-float pairs:                            */
 /*     (r_hi[i], r_lo[i]) = OP((a_hi[i], a_lo[i]), (b_hi[i], b_lo[i]))      */
-/* All ten planes hold n binary32 values.  Results are bit-identical to the */
-/* documented binary32 operation sequence.  Errors: FF_ERR_SIZE (n < 0),    */
-/* FF_ERR_NULL (a NULL plane, n > 0), FF_ERR_ALIGN, FF_ERR_HIP.             */
+/* All six planes (four in, two out) hold n binary32 values.  Results are  */
+/* bit-identical to the documented binary32 operation sequence, whatever   */
+/* the alignment and launch form (float4 groups below 2^22 elements when   */
+/* every plane is 16-byte aligned, 4-byte accesses otherwise).  Errors:    */
+/* FF_ERR_SIZE (n < 0), FF_ERR_NULL (a NULL plane, n > 0), FF_ERR_ALIGN,   */
+/* FF_ERR_HIP.                                                              */
 /* ------------------------------------------------------------------------ */
 
 /* Add22 (section 4.1, Add22 theorem): r = ah (+) bh; if |ah| >= |bh| then
