@@ -126,7 +126,6 @@ constexpr int kP = 8 * kS - 2;        // fixed-point bits: |X| <= 2^kP
 constexpr int kTile = 64;             // rows (A) / columns (B) per tile
 constexpr int kRowBytes = 32;         // digit bytes of one tile row per K-stage
 constexpr int kTileBytes = kTile * kRowBytes;       // 2 KiB
-constexpr int kStageBytes = 2 * kS * kTileBytes;    // A and B tiles of all slices: 28 KiB
 constexpr int kEpiShift = 8 * (kS - 1) - 2 * kP;   // C = T 2^(e + f + kEpiShift)
 constexpr int64_t kMaxKChunk = 16384; // int32 accumulators stay exact below this
 
