@@ -8,8 +8,9 @@ operations per second (4 N per step).
 Printed: ONE JSON line on stdout, with
   * ``roofline`` for the dominant kernel (algorithmic bytes / average launch
     time from HIP events recorded on the launch stream, against 8 TB/s),
-  * ``cpu_baseline``: the oracle (single-threaded C) timed on this host on a
-    bounded sample of the same inputs.
+  * ``cpu_baseline``: the oracle (C) timed on this host on a bounded sample of
+    the same inputs, on up to 16 host threads over disjoint pieces of the
+    sample (``cores``), with its single-threaded rate beside it.
 Progress goes to stderr.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -119,6 +120,56 @@ def _oracle_timed(fn):
     return time.perf_counter() - t0
 
 
+def _host_threads() -> int:
+    """Host threads for the CPU baseline: the CPUs this process may run on,
+    at most 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _chunks(n: int, parts: int):
+    """[lo, hi) bounds of `parts` near-equal contiguous pieces of range(n)."""
+    return [(n * k // parts, n * (k + 1) // parts) for k in range(parts)]
+
+
+def _oracle_parallel(tasks) -> tuple[float, int]:
+    """Wall seconds to run the oracle calls `tasks` (zero-argument callables
+    on disjoint pieces of one sample) on _host_threads() threads, and that
+    thread count.  The oracle is unchanged: its C entry points release the
+    interpreter lock, so the pieces run concurrently, like static chunks of a
+    parallel loop."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    threads = _host_threads()
+    with ThreadPoolExecutor(threads) as pool:
+        list(pool.map(lambda f: f(), [lambda: None] * threads))   # threads started
+        t0 = time.perf_counter()
+        list(pool.map(lambda f: f(), tasks))
+        dt = time.perf_counter() - t0
+    return dt, threads
+
+
+def _baseline(value_mt, threads, value_st, unit, sample) -> dict:
+    """The cpu_baseline object: the oracle on `threads` host threads, with the
+    single-threaded rate of the same sample beside it."""
+    return {"value": value_mt, "unit": unit, "cores": threads, "kind": "oracle",
+            "sample": sample, "single_thread_value": value_st, "host_cpu": _host_cpu()}
+
+
 def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
     """The other float-float workloads, one line each (not part of the step)."""
     import torch
@@ -197,9 +248,13 @@ def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
         m = 1 << 23
         xs, cs = x[:m].cpu().numpy(), coef.cpu().numpy()
         dt = _oracle_timed(lambda: oracle.horner_comp(cs, xs))
-        horner["cpu_baseline"] = {"value": m / dt, "unit": "points/s (compensated Horner)",
-                                  "cores": 1, "kind": "oracle",
-                                  "sample": f"first {m} points, single-threaded C oracle, {dt:.2f} s"}
+        xa = x.cpu().numpy()
+        dtp, th = _oracle_parallel([lambda lo=lo, hi=hi: oracle.horner_comp(cs, xa[lo:hi])
+                                    for lo, hi in _chunks(n, 4 * _host_threads())])
+        horner["cpu_baseline"] = _baseline(
+            n / dtp, th, m / dt, "points/s (compensated Horner)",
+            f"all {n} points in {4 * th} contiguous pieces, C oracle on {th} host threads, "
+            f"{dtp:.2f} s (one thread: first {m} points, {dt:.2f} s)")
     out["horner_2p26"] = horner
     del coef, x, y, yff
     torch.cuda.empty_cache()
@@ -248,10 +303,21 @@ def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
         e = int(offs_h[nv])
         xs, ys = x[:e].cpu().numpy(), y[:e].cpu().numpy()
         dt = _oracle_timed(lambda: oracle.dot_seq_batched(xs, ys, offs_h[:nv + 1]))
-        out["dot_batched"]["cpu_baseline"] = {
-            "value": e / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {nv} vectors ({e} elements), sequential Add22 dot, "
-                      f"single-threaded C oracle, {dt:.2f} s"}
+        del xs, ys
+        xa, ya = x.cpu().numpy(), y.cpu().numpy()
+        nall = offs_h.size - 1
+
+        def piece(v0, v1):
+            o0, o1 = int(offs_h[v0]), int(offs_h[v1])
+            return lambda: oracle.dot_seq_batched(xa[o0:o1], ya[o0:o1], offs_h[v0:v1 + 1] - o0)
+
+        dtp, th = _oracle_parallel([piece(v0, v1) for v0, v1 in _chunks(nall, 4 * _host_threads())])
+        out["dot_batched"]["cpu_baseline"] = _baseline(
+            total / dtp, th, e / dt, "elements/s",
+            f"all {nall} vectors ({total} elements), sequential Add22 dot per vector, vectors "
+            f"in {4 * th} pieces, C oracle on {th} host threads, {dtp:.2f} s (one thread: "
+            f"first {nv} vectors, {e} elements, {dt:.2f} s)")
+        del xa, ya
     del x, y, offs, res, ws
     torch.cuda.empty_cache()
 
@@ -279,12 +345,17 @@ def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
         Ah, Al = A[0, :r].cpu().numpy(), A[1, :r].cpu().numpy()
         Bh, Bl = B[0, :, :r].contiguous().cpu().numpy(), B[1, :, :r].contiguous().cpu().numpy()
         dt = _oracle_timed(lambda: oracle.gemm_ff_seq(Ah, Al, Bh, Bl))
-        rate = 2.0 * r * r * n / dt
-        gemm["cpu_baseline"] = {"value": rate / 1e12, "unit": "ff_TFLOP/s", "cores": 1,
-                                "kind": "oracle",
-                                "sample": f"{r} x {r} block of C at K = {n} (plain Add22/Mul22 "
-                                          f"loop, single-threaded C oracle, {dt:.2f} s; 4096^3 "
-                                          f"would take {flops / rate:.0f} s)"}
+        th = _host_threads()
+        rp = r * th                                           # 192 rows of C per thread
+        Aph, Apl = A[0, :rp].cpu().numpy(), A[1, :rp].cpu().numpy()
+        dtp, th = _oracle_parallel([lambda lo=lo, hi=hi: oracle.gemm_ff_seq(Aph[lo:hi], Apl[lo:hi], Bh, Bl)
+                                    for lo, hi in _chunks(rp, th)])
+        rate, rate1 = 2.0 * rp * r * n / dtp, 2.0 * r * r * n / dt
+        gemm["cpu_baseline"] = _baseline(
+            rate / 1e12, th, rate1 / 1e12, "ff_TFLOP/s",
+            f"{rp} x {r} block of C at K = {n} (plain Add22/Mul22 loop), rows in {th} pieces, "
+            f"C oracle on {th} host threads, {dtp:.2f} s (one thread: {r} x {r}, {dt:.2f} s); "
+            f"4096^3 would take {flops / rate:.0f} s")
     out["gemm_4096"] = gemm
     del A, B, C
     torch.cuda.empty_cache()
@@ -310,10 +381,12 @@ def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
         Ah, Al = A[0, :r].cpu().numpy(), A[1, :r].cpu().numpy()
         xh, xl = xv[0].cpu().numpy().reshape(m, 1), xv[1].cpu().numpy().reshape(m, 1)
         dt = _oracle_timed(lambda: oracle.gemm_ff_seq(Ah, Al, xh, xl))
-        mv["cpu_baseline"] = {"value": 8 * r * m / dt / 1e9, "unit": "forward GB/s of A",
-                              "cores": 1, "kind": "oracle",
-                              "sample": f"all {r} rows of y = A x (sequential Add22 of Mul22 "
-                                        f"terms, single-threaded C oracle, {dt:.2f} s)"}
+        dtp, th = _oracle_parallel([lambda lo=lo, hi=hi: oracle.gemm_ff_seq(Ah[lo:hi], Al[lo:hi], xh, xl)
+                                    for lo, hi in _chunks(r, 4 * _host_threads())])
+        mv["cpu_baseline"] = _baseline(
+            8 * r * m / dtp / 1e9, th, 8 * r * m / dt / 1e9, "forward GB/s of A",
+            f"all {r} rows of y = A x (sequential Add22 of Mul22 terms), rows in {4 * th} "
+            f"pieces, C oracle on {th} host threads, {dtp:.2f} s ({dt:.2f} s on one)")
     out["matvec_8192"] = mv
     del A, xv, g
     torch.cuda.empty_cache()
@@ -342,14 +415,20 @@ def cpu_baseline(a, b, target_s: float):
     for op in OPS:
         oracle.elementwise(op, ah, al, bh, bl, out=(rh, rl))
     dt = time.perf_counter() - t0
-    return {
-        "value": 4 * n / dt,
-        "unit": "ff ops/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": f"first {n} of the {n_total} pairs, ops add/sub/mul/div once each "
-                  f"({4 * n} ff ops in {dt:.2f} s, single-threaded C oracle)",
-    }
+
+    def piece(lo, hi):
+        def run():
+            for op in OPS:
+                oracle.elementwise(op, ah[lo:hi], al[lo:hi], bh[lo:hi], bl[lo:hi],
+                                   out=(rh[lo:hi], rl[lo:hi]))
+        return run
+
+    dtp, th = _oracle_parallel([piece(lo, hi) for lo, hi in _chunks(n, _host_threads())])
+    return _baseline(
+        4 * n / dtp, th, 4 * n / dt, "ff ops/s",
+        f"first {n} of the {n_total} pairs, ops add/sub/mul/div once each ({4 * n} ff ops), "
+        f"pairs in {th} contiguous pieces, C oracle on {th} host threads, {dtp:.2f} s "
+        f"({dt:.2f} s on one)")
 
 
 def main(argv=None) -> int:
