@@ -470,8 +470,9 @@ ff_status resolve_cfg(const ff_dot_cfg *cfg, Cfg &out)
 int default_grid()
 {
     int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess)
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;  // MI355X's count when the query fails
     return 8 * (cus > 0 ? cus : 256);
 }
 
@@ -665,8 +666,9 @@ ff_status ff_dot_batched_autotune(const float *x, const float *y, const int64_t 
     if (hipEventCreate(&e0) != hipSuccess)
         return ffh::hip_failure(hipGetLastError());
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
-        return ffh::hip_failure(hipGetLastError());
+        const ff_status failed = ffh::hip_failure(hipGetLastError());
+        (void)hipEventDestroy(e0);
+        return failed;
     }
     ff_status status = FF_OK;
     float best_time = -1.0f;
@@ -682,19 +684,21 @@ ff_status ff_dot_batched_autotune(const float *x, const float *y, const int64_t 
                                             out_hi, out_lo, stream);
                     if (status != FF_OK)
                         goto done;
-                    hipEventRecord(e0, st);
-                    for (int r = 0; r < reps && status == FF_OK; ++r)
-                        status = ff_dot_batched(x, y, offsets, nvec, total_len, &c, ws, ws_bytes,
-                                                out_hi, out_lo, stream);
-                    hipEventRecord(e1, st);
-                    if (status != FF_OK)
-                        goto done;
-                    if (hipEventSynchronize(e1) != hipSuccess) {
+                    if (hipEventRecord(e0, st) != hipSuccess) {
                         status = ffh::hip_failure(hipGetLastError());
                         goto done;
                     }
+                    for (int r = 0; r < reps && status == FF_OK; ++r)
+                        status = ff_dot_batched(x, y, offsets, nvec, total_len, &c, ws, ws_bytes,
+                                                out_hi, out_lo, stream);
+                    if (status != FF_OK)
+                        goto done;
                     float ms = 0.0f;
-                    hipEventElapsedTime(&ms, e0, e1);
+                    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                        status = ffh::hip_failure(hipGetLastError());
+                        goto done;
+                    }
                     ms /= reps;
                     if (best_time < 0.0f || ms < best_time) {
                         best_time = ms;
@@ -705,8 +709,8 @@ ff_status ff_dot_batched_autotune(const float *x, const float *y, const int64_t 
         status = FF_ERR_WORKSPACE;
     *best_ms = best_time;
 done:
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     return status;
 }
 
