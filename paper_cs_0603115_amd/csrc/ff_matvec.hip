@@ -389,8 +389,9 @@ __global__ __launch_bounds__(256) void dot_backward(const float *__restrict__ g_
 // One workgroup per block of kBwdBlock consecutive elements, launched in
 // order, so that the resident workgroups sweep memory together.  The
 // workgroup finds, by two binary searches over the (clamped) offsets, the
-// vectors owning its first and last element, and when they are at most
-// kBwdWin apart copies their offsets and gradients into LDS.  Thread t then
+// vectors owning its first and last element, and when that window holds
+// between one and kBwdWin vectors copies their offsets and gradients into
+// LDS.  Thread t then
 // takes elements b0 + t + 256 k (each wavefront access is 256 contiguous
 // bytes of a plane) in increasing order, advancing its own vector index as
 // they cross vector starts.  (A block spanning more vectors -- tiny vectors
@@ -446,7 +447,7 @@ __global__ __launch_bounds__(kBwdThreads) void dot_batched_bwd(
     const int64_t va = v_first > 0 ? v_first : 0;
     const int64_t vb = v_last < nvec - 1 ? v_last : nvec - 1;
     const int64_t count = vb >= va ? vb - va + 1 : 0;
-    const bool in_lds = count <= kBwdWin;
+    const bool in_lds = count > 0 && count <= kBwdWin;
     if (in_lds) {
         for (int64_t j = t; j <= count; j += kBwdThreads) {
             s_off[j] = clamped_offset(offsets, va + j, total);
@@ -460,11 +461,16 @@ __global__ __launch_bounds__(kBwdThreads) void dot_batched_bwd(
 
     auto run = [&](auto lds_tag) {
         constexpr bool kLds = decltype(lds_tag)::value;
+        // With non-decreasing offsets every lookup falls inside the window
+        // (w - va <= count, v - va < count); the clamps only keep offsets
+        // that break that order from reading past it.
         auto start_of = [&](int64_t w) -> int64_t {
-            if constexpr (kLds)
-                return s_off[w - va];
-            else
+            if constexpr (kLds) {
+                const int64_t j = w - va;
+                return s_off[j < count ? j : count];
+            } else {
                 return clamped_offset(offsets, w, total);
+            }
         };
         // all of this thread's operands first: sixteen independent loads
         // per plane in flight
@@ -496,8 +502,10 @@ __global__ __launch_bounds__(kBwdThreads) void dot_batched_bwd(
                 if (v != gv) {
                     gv = v;
                     if constexpr (kLds) {
-                        gh = s_gh[v - va];
-                        gl = s_gl[v - va];
+                        const int64_t j = v - va;
+                        const int64_t jc = j < count ? j : count - 1;
+                        gh = s_gh[jc];
+                        gl = s_gl[jc];
                     } else {
                         gh = g_hi[v];
                         gl = g_lo[v];

@@ -162,3 +162,46 @@ def test_autograd_against_fp64_gradient_and_finite_differences():
         xm[i] -= h
         fd = (loss(xp) - loss(xm)) / (2 * h)
         assert abs(fd - dx[i]) <= 1e-9 * max(1.0, abs(fd)), (i, fd, dx[i])
+
+
+def _candidates_hold(d, g, y_h, y_l):
+    """Every element of the gradient pair d is Mul22(g_v, y_i) for some v, or
+    a zero pair: the property the entry point keeps for offsets that break
+    their non-decreasing order (which vector owns an element is then
+    unspecified, but only real gradients or zeros are written)."""
+    n = y_h.size
+    ok = (d[0] == 0) & (d[1] == 0)
+    for v in range(g.shape[1]):
+        ch, cl = oracle.elementwise("mul", np.full(n, g[0, v], np.float32),
+                                    np.full(n, g[1, v], np.float32), y_h, y_l)
+        ok |= same_bits_mask(d[0], ch) & same_bits_mask(d[1], cl)
+    return ok
+
+
+def same_bits_mask(a, b):
+    return a.view(np.int32) == b.view(np.int32)
+
+
+@pytest.mark.parametrize("case", ["shuffled_small", "out_of_range", "shuffled_wide"])
+def test_offsets_out_of_order_write_only_real_gradients(case):
+    _announce(f"[gpu] dot backward with offsets out of order: {case}")
+    rng = np.random.default_rng(5011)
+    if case == "shuffled_small":
+        total, offs = 5000, np.array([100, 3000, 800, 4999, 2, 4000], np.int64)
+    elif case == "out_of_range":
+        total, offs = 7001, np.array([-9, 7100, -1, 50, 7001, 1 << 40], np.int64)
+    else:
+        # 600 vectors, starts shuffled: windows wider than the LDS copy
+        total = 300007
+        offs = np.sort(rng.integers(0, total + 1, 601)).astype(np.int64)
+        rng.shuffle(offs[100:500])
+    nvec = offs.size - 1
+    x = fi.random_ff(total, 5012, -20, 20)
+    y = fi.random_f32(total, 5013, -20, 20)
+    g = fi.random_ff(nvec, 5014, -4, 4)
+    dx, dy = _run(g.cuda(), x.cuda(), y.cuda(), torch.from_numpy(offs).cuda())
+    gn = g.numpy()
+    yh, yl = _planes(y)
+    xh, xl = _planes(x)
+    assert _candidates_hold(dx, gn, yh, yl).all()
+    assert _candidates_hold(dy, gn, xh, xl).all()
