@@ -54,7 +54,8 @@ typedef int32_t ff_status;
 #define FF_ERR_SIZE        2 /* negative or inconsistent size / dimension   */
 #define FF_ERR_ALIGN       3 /* pointer not aligned to its element type     */
 #define FF_ERR_WORKSPACE   4 /* workspace missing or smaller than required  */
-#define FF_ERR_UNSUPPORTED 5 /* device is not gfx950, or option unsupported */
+#define FF_ERR_UNSUPPORTED 5 /* the launch found no gfx950 code for the     */
+                             /* current device                              */
 #define FF_ERR_HIP         6 /* the HIP runtime reported an error (launch)  */
 #define FF_ERR_ARG         7 /* invalid enumeration value or option         */
 
@@ -118,7 +119,8 @@ ff_status ff_mul_dekker(const float *a_hi, const float *a_lo,
  * for Split and Mul12): c = ah (/) bh; (u, uu) = c*bh exactly (FMA);
  * cc = ((((ah (-) u) (-) uu) (+) al) (-) (c (x) bl)) (/) bh;
  * result Add12(c, cc).  (/) is correctly rounded binary32 division.
- * Relative error <= 2^-44 (measured, see the test-suite). */
+ * Relative error <= 2^-44 is the tested bar; no proof is claimed (the worst
+ * measured on 2^24 random pairs of either workload is 2^-45.0). */
 ff_status ff_div(const float *a_hi, const float *a_lo, const float *b_hi,
                  const float *b_lo, float *r_hi, float *r_lo, int64_t n,
                  void *stream);
@@ -189,7 +191,8 @@ ff_status ff_div_accurate(const float *a_hi, const float *a_lo,
  * Different cfg values may give different (equally valid) last bits.
  *
  * Accuracy: |result - exact| is bounded by (tree depth) * 2^-44 * sum|x_i y_i|
- * in the worst case; on random data it is far smaller (see the test-suite).
+ * in the worst case; on random data it is far smaller (2^-47.1 sum|x_i y_i|
+ * at worst over a batch of 4096 vectors of 64 to 2^20 normal(0,1) terms).
  */
 
 /* Launch shape of the batched dot.  All-zero fields select the defaults. */
@@ -294,7 +297,8 @@ ff_status ff_dot_batched_autotune(const float *x, const float *y,
  * dimension lda >= N (elements); vectors are float-float planes.  Every term
  * is a Mul22 product (FMA TwoProd) and sums use Add22 (section 4.1).
  *
- * algo FF_MATVEC_FAST  -- tiled kernels: one workgroup per row (forward);
+ * algo FF_MATVEC_FAST  -- tiled kernels: one workgroup per pair of rows
+ *                         sharing each load of x (forward);
  *                         one fused pass over A writing dA and per-band
  *                         partial column sums of A^T g (backward), combined
  *                         in band order by a second small launch.
@@ -412,10 +416,6 @@ ff_status ff_gemm(int64_t M, int64_t N, int64_t K, const float *A_hi,
                   void *stream);
 
 /* ------------------------------------------------------------------------ */
-/* Measurement probe                                                        */
-/* ------------------------------------------------------------------------ */
-
-/* ------------------------------------------------------------------------ */
 /* Error-free transforms and binary32 reference operators                   */
 /* ------------------------------------------------------------------------ */
 /*
@@ -434,8 +434,10 @@ ff_status ff_gemm(int64_t M, int64_t N, int64_t K, const float *A_hi,
  *   ff_f32_mad       r_i = fma(a_i, b_i, c_i), one rounding (the tables'
  *                    "Mad"; gfx950 has no unfused binary32 multiply-add)
  * All pointers: device, caller-owned, n binary32 words each; an output may
- * alias an input exactly (in place), partial overlap is undefined.  When
- * every pointer is 16-byte aligned the float4 path runs.
+ * alias an input exactly (in place), partial overlap is undefined.  Below
+ * 2^22 elements, when every pointer is 16-byte aligned, a float4 path runs;
+ * otherwise 4-byte accesses, one lane-contiguous element per lane and
+ * plane at a time.  Results do not depend on the path.
  * Errors: FF_ERR_SIZE (n < 0), FF_ERR_NULL, FF_ERR_ALIGN (a pointer not
  * 4-byte aligned), FF_ERR_HIP.  n = 0 is a no-op. */
 ff_status ff_add12(const float *a, const float *b, float *s, float *r,
@@ -511,9 +513,15 @@ ff_status ff_from_f64(const double *x, float *hi, float *lo, int64_t n,
 ff_status ff_to_f64(const float *hi, const float *lo, double *x, int64_t n,
                     void *stream);
 
-/* dst[i] = src[i] for i < n (binary32), with the same load/store pattern as
- * the elementwise operators: the HBM bandwidth reference for roofline and
- * counter calibration.  Errors as for the elementwise operators. */
+/* ------------------------------------------------------------------------ */
+/* Measurement probe                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* dst[i] = src[i] for i < n (binary32): the streaming reference for the
+ * roofline and the HBM counter calibration.  One float4 group per lane with
+ * non-temporal loads and stores when both pointers are 16-byte aligned (the
+ * fastest copy measured on MI355X), 4-byte accesses for the tail and
+ * otherwise.  Errors as for the elementwise operators. */
 ff_status ff_copy(const float *src, float *dst, int64_t n, void *stream);
 
 #ifdef __cplusplus

@@ -41,9 +41,12 @@ const char *ff_status_str(ff_status status)
 
 int32_t ff_abi_version(void) { return FF_ABI_VERSION; }
 
+#define FF_STRINGIFY_(x) #x
+#define FF_STRINGIFY(x) FF_STRINGIFY_(x)
+
 const char *ff_build_info(void)
 {
-    return "libff abi=" "1"
+    return "libff abi=" FF_STRINGIFY(FF_ABI_VERSION)
            "; target=gfx950"
            "; fp-contract=off"
            "; f32-denormals=preserve"
