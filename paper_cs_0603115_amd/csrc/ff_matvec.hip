@@ -7,10 +7,11 @@
 // (16 bytes per element) with Mul22 (dA) + Mul22 + Add22 (dx) (~38 VALU).
 // Both are HBM-bound on gfx950 (ridge ~9.8 binary32 operations per byte).
 //
-// Fast forward: one workgroup per row; lane t takes float4 groups t,
-// t + BLOCK, ... of the row (coalesced 1 KiB per wavefront load), keeps four
-// Add22 accumulators (one per float4 component), then a wavefront butterfly
-// and an in-order LDS combine give y_i.  x is re-read from L2 by every row.
+// Fast forward: one workgroup per pair of rows; lane t takes float4 groups
+// t, t + BLOCK, ... of both rows (coalesced 1 KiB per wavefront load), each
+// load of x serving both, keeps four Add22 accumulators per row (one per
+// float4 component), then a wavefront butterfly and an in-order LDS combine
+// give y_i.  x is re-read from L2 by every pair of rows.
 // Fast backward: the workgroup grid is (column tiles) x (row bands); a
 // thread owns four adjacent columns, walks the rows of its band, writes
 // dA_ij = Mul22(g_i, x_j) and accumulates Mul22(g_i, A_ij) per column; the

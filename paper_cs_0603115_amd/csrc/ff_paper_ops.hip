@@ -7,7 +7,8 @@
 //
 // Same streaming structure as the float-float operators: 1024-thread
 // workgroups in launch order, two lane-contiguous elements per thread and
-// plane, all 4-byte non-temporal loads issued before the arithmetic, any
+// plane, all 4-byte non-temporal loads issued before the arithmetic (plane
+// by plane where the kernel writes two planes), any
 // 4-byte alignment; one float4 group per plane and thread below 2^22
 // elements.  Bytes per element: 12 (add, mul), 16 (mad, Add12,
 // Mul12); all HBM-bound at large n, launch-bound at the paper's sizes.

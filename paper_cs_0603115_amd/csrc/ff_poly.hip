@@ -18,8 +18,11 @@
 //
 // Cost per point and degree: 2 floating-point operations (Horner), 11
 // (CompHorner: TwoProd 2, TwoSum 6, correction 3), 23 (Mul22 12 + Add22 11,
-// plus Add22's compare-and-select); 8 to 16 bytes of memory per point.  At
-// any degree above 2 the kernels are bound by the VALU, not by HBM.
+// plus Add22's compare-and-select); 8 bytes of memory per point for the
+// binary32 forms, 12 for float-float Horner at binary32 points.  Against
+// gfx950's ridge of ~9.8 binary32 operations per byte, binary32 Horner stays
+// HBM-bound up to degree ~39, while CompHorner (above degree ~7) and
+// float-float Horner (above degree ~5) are bound by the VALU.
 #include "ff_device.h"
 #include "ff_host.h"
 
