@@ -390,10 +390,16 @@ ff_status ff_dot_batched_backward(const float *g_hi, const float *g_lo,
  *                     |d| <= 128) and FP32 matrix-core accumulation, whose
  *                     partial sums are moved to integer accumulators before
  *                     they can exceed 2^24 (so they stay exact).
- * Sliced accuracy: |C_ij - exact| <= 2^-44 * (|A| |B|)_ij for inputs whose
- * rows/columns do not span extreme dynamic ranges (the digit rounding
- * contributes at most 2^(e_i - 54) sum_k |B_kj| + 2^(f_j - 54) sum_k |A_ik|,
- * with 2^e_i the power of two above row i's largest |A_ik|, 2^f_j likewise).
+ * Sliced accuracy: |C_ij - exact| <= 2^-44 * (|A| |B|)_ij when the rows of
+ * A and columns of B do not span extreme dynamic ranges (normal(0,1) data at
+ * 4096^3: 2^-51.6 at worst).  In general, with 2^e_i the power of two above
+ * row i's largest |A_ik| and 2^f_j the one above column j's largest |B_kj|:
+ *   |C_ij - exact| <= 2^(e_i - 54) sum_k |B_kj|
+ *                   + 2^(f_j - 54) sum_k (|A_ik| + 2^(e_i - 54))
+ *                   + K 2^(e_i + f_j - 47) + 2^-47 |C_ij|
+ * (digit rounding, dropped digit pairs, final rounding).  Rows and columns
+ * spanning 40 binades measured 2^-11.3 normwise, inside this bound; the FMA
+ * loop has no such limit.
  * Inputs must be finite float-float numbers with |lo| <= ulp(hi).
  * Workspace: 0 bytes for the FMA loop; digit planes (7 (M+N) K bytes for
  * int8, twice that for BF16, rounded up to 64-row / 64-byte tiles) plus

@@ -6,7 +6,8 @@
   (long accumulator) entry by entry, normwise |C - exact| <= 2^-44 (|A||B|);
   exactly equal to each other (both sum the same digit products exactly);
   exact on integer data and on A times the identity when every row of A sits
-  in one binade.
+  in one binade; on rows and columns spanning 40 binades, within the bound
+  the algorithm documents for that case.
 """
 import math
 import sys
@@ -179,6 +180,65 @@ def test_full_size_4096():
     assert same_bits(Cpn[0], Ch) and same_bits(Cpn[1], Cl)
     del A, B, C8, C16, Cp
     torch.cuda.empty_cache()
+
+
+def _wide_range_operands(M, K, N, seed):
+    """Rows of A and columns of B spanning 40 binades: half the rows (and
+    columns) have every entry scaled by 2^s, s uniform in {-40..0}; the other
+    half hold one normal(0,1) entry among entries scaled by 2^-40.  Scaling
+    by powers of two keeps both words exact."""
+    rng = np.random.default_rng(seed)
+    A = fi.gaussian_ff((M, K), seed).double()
+    B = fi.gaussian_ff((K, N), seed + 1).double()
+    sa = rng.integers(-40, 1, (M, K)).astype(np.float64)
+    sa[M // 2:] = -40.0
+    sa[np.arange(M // 2, M), rng.integers(0, K, M - M // 2)] = 0.0
+    sb = rng.integers(-40, 1, (K, N)).astype(np.float64)
+    sb[:, N // 2:] = -40.0
+    sb[rng.integers(0, K, N - N // 2), np.arange(N // 2, N)] = 0.0
+    A = (A * torch.from_numpy(np.exp2(sa))).float()
+    B = (B * torch.from_numpy(np.exp2(sb))).float()
+    return A, B
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_wide_dynamic_range_within_the_documented_bound(algo):
+    # Rows and columns whose entries span 40 binades, where the normwise
+    # 2^-44 target is not promised: every entry must still meet the bound the
+    # algorithm documents, |C - exact| <= 2^(e_i - 54) sum_k |B_kj|
+    # + 2^(f_j - 54) sum_k (|A_ik| + 2^(e_i - 54))   (digit rounding)
+    # + K 2^(e_i + f_j - 47)                          (dropped digit pairs)
+    # + 2^-47 |C|                                     (final rounding),
+    # with 2^e_i above row i's largest |A_ik| and 2^f_j above column j's
+    # largest |B_kj| (taken one binade higher here, for either convention).
+    M, K, N = 32, 2048, 32
+    _announce(f"[gpu] gemm wide dynamic range {M}x{K}x{N} ({algo})")
+    A, B = _wide_range_operands(M, K, N, 7301)
+    C = _ff().ff_gemm(A.cuda(), B.cuda(), algo=_algo(algo)).cpu().numpy()
+    An, Bn = A.numpy(), B.numpy()
+    Av = An[0].astype(np.float64) + An[1].astype(np.float64)
+    Bv = Bn[0].astype(np.float64) + Bn[1].astype(np.float64)
+    e = np.frexp(np.abs(Av).max(axis=1))[1] + 1
+    f = np.frexp(np.abs(Bv).max(axis=0))[1] + 1
+    ri, ci = np.meshgrid(np.arange(M), np.arange(N), indexing="ij")
+    ri, ci = ri.ravel(), ci.ravel()
+    exact = oracle.exact_gemm_entries(An[0], An[1], Bn[0], Bn[1], ri, ci)
+    scale = oracle.exact_absgemm_entries(An[0], An[1], Bn[0], Bn[1], ri, ci)
+    sumB = np.abs(Bv).sum(axis=0)
+    sumA = np.abs(Av).sum(axis=1)
+    worst_ratio, worst_normwise = 0.0, -math.inf
+    for t, (i, j) in enumerate(zip(ri, ci)):
+        err = abs(frac(C[0, i, j]) + frac(C[1, i, j]) - exact[t])
+        bound = (math.ldexp(sumB[j], int(e[i]) - 54)
+                 + math.ldexp(sumA[i] + K * math.ldexp(1.0, int(e[i]) - 54), int(f[j]) - 54)
+                 + K * math.ldexp(1.0, int(e[i] + f[j]) - 47)
+                 + math.ldexp(abs(float(exact[t])), -47)) * 1.001
+        assert float(err) <= bound, (algo, i, j, float(err), bound)
+        worst_ratio = max(worst_ratio, float(err) / bound)
+        if err and scale[t]:
+            worst_normwise = max(worst_normwise, math.log2(err / scale[t]))
+    _announce(f"  worst error / documented bound {worst_ratio:.3g}; "
+              f"worst normwise log2 error {worst_normwise:.1f}")
 
 
 @pytest.mark.parametrize("algo", ALGOS + ["fma"])
