@@ -182,6 +182,34 @@ def test_full_size_4096():
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("algo", ALGOS + ["fma"])
+def test_zero_rows_columns_and_power_of_two_maxima(algo):
+    # an all-zero row of A and column of B (no largest entry to scale by)
+    # give exact zero words; rows and columns whose largest magnitude is an
+    # exact power of two (the boundary of the scale choice) and rows holding
+    # a single nonzero entry stay within the normwise bound
+    M, K, N = 70, 129, 66
+    _announce(f"[gpu] gemm zero rows/columns and power-of-two maxima ({algo})")
+    A = fi.gaussian_ff((M, K), 7401)
+    B = fi.gaussian_ff((K, N), 7402)
+    A[:, 3] = 0.0
+    B[:, :, 5] = 0.0
+    A[:, 10] = 0.0
+    A[0, 10, 17] = 2.0 ** 7                      # a single power-of-two entry
+    A[:, 11] = A[:, 11] * 2.0 ** -4              # |entries| < 1, then
+    A[0, 11, 40], A[1, 11, 40] = -1.0, 0.0       # largest entry exactly -1
+    B[:, :, 7] = B[:, :, 7] * 2.0 ** -7          # |entries| < 2^-3, then
+    B[0, 64, 7], B[1, 64, 7] = 2.0 ** -3, 0.0    # largest entry exactly 2^-3
+    A, B = A.cuda(), B.cuda()
+    C = _ff().ff_gemm(A, B, algo=_algo(algo))
+    torch.cuda.synchronize()
+    Cn = C.cpu().numpy()
+    assert np.all(Cn[:, 3, :] == 0) and np.all(Cn[:, :, 5] == 0)
+    rows = [0, 3, 10, 11, M - 1]
+    cols = [0, 5, 7, 33, N - 1]
+    check_entries(A, B, C, rows, cols, f"zero/pow2 {algo}")
+
+
 def _wide_range_operands(M, K, N, seed):
     """Rows of A and columns of B spanning 40 binades: half the rows (and
     columns) have every entry scaled by 2^s, s uniform in {-40..0}; the other
