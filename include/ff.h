@@ -506,7 +506,9 @@ ff_status ff_horner_ff(const float *coef_hi, const float *coef_lo,
 /*
  * ff_from_f64: hi_i = fl32(x_i), lo_i = fl32(x_i - hi_i) (the difference is
  *   exact in binary64), so hi + lo = x to within 2^-48 |x| for x in the
- *   binary32 normal range; |x| beyond the binary32 range gives hi = +-inf.
+ *   binary32 normal range.  Outside it the same sequence gives pairs that are
+ *   not float-float numbers: x = +-inf gives (x, NaN); a finite x that rounds
+ *   past the binary32 maximum gives (+-inf, -+inf); NaN gives (NaN, NaN).
  * ff_to_f64: x_i = (double) hi_i + (double) lo_i, one binary64 rounding
  *   (exact whenever the pair's bits fit in 53).
  * Pointers: device, caller-owned; binary64 plane 8-byte aligned, binary32

@@ -1,8 +1,9 @@
 """GPU parity of the binary64 <-> float-float conversions: every word bit
 for bit against the oracle, on wide exponent ranges (low words down to the
 subnormal range, signed zeros), ragged sizes, unaligned planes (the
-one-per-lane kernel) and a 2^24-element run; the Python short names are the
-same entry points."""
+one-per-lane kernel) and a 2^24-element run; infinities, NaN and values
+beyond the binary32 range on both launch forms; the Python short names are
+the same entry points."""
 import sys
 
 import numpy as np
@@ -67,3 +68,36 @@ def test_unaligned_planes_and_short_names():
     a, b, _ = fi.mixed_ff_pair(1000, 2302, device="cuda")
     assert torch.equal(ff.add(a, b), ff.ff_add(a, b))
     assert torch.equal(ff.div(a, b), ff.ff_div(a, b))
+
+
+def _same_or_both_nan(a, b, view):
+    """Bitwise equal, except that any NaN matches any NaN (NaN payloads are
+    not specified by IEEE arithmetic and differ between the GPU and x86)."""
+    both_nan = np.isnan(a) & np.isnan(b)
+    return bool(np.all(both_nan | (a.view(view) == b.view(view))))
+
+
+@pytest.mark.parametrize("vec", [True, False])
+def test_special_values_match_the_oracle(vec):
+    # infinities, NaN, FLT_MAX, the binary32 overflow threshold and its
+    # neighbour, finite values beyond binary32, signed zeros, values below the
+    # smallest subnormal, on both launch forms (float4 groups when aligned)
+    print(f"[gpu] conversions of special values (vec={vec})", file=sys.stderr, flush=True)
+    ff = _ff()
+    fmax = float(np.finfo(np.float32).max)
+    thresh = fmax + 2.0 ** 103
+    base = np.array([np.inf, -np.inf, np.nan, fmax, -fmax, thresh, -thresh,
+                     np.nextafter(thresh, 0.0), 1e39, -1e300, 0.0, -0.0, 5e-324, 1e-46,
+                     1e-40, -3e-39], dtype=np.float64)
+    x = np.tile(base, 9)                                   # 144 values: whole float4 groups
+    xd = torch.from_numpy(x).cuda() if vec else torch.from_numpy(np.r_[0.0, x]).cuda()[1:]
+    got = ff.ff_from_f64(xd) if vec else ff.ff_from_f64(
+        xd, out=ff.ff_zeros((x.size + 1,), device="cuda")[:, 1:])
+    torch.cuda.synchronize()
+    g = got.cpu().numpy()
+    hi, lo = oracle.from_f64(x)
+    assert _same_or_both_nan(g[0], hi, np.uint32) and _same_or_both_nan(g[1], lo, np.uint32)
+    # and back: the same pairs (including inf / NaN words) joined in binary64
+    pairs = torch.from_numpy(np.stack([hi, lo]))
+    back = ff.ff_to_f64(pairs.cuda()).cpu().numpy()
+    assert _same_or_both_nan(back, oracle.to_f64(hi, lo), np.uint64)

@@ -63,3 +63,52 @@ def test_round_trip_where_the_bits_fit():
             h2, l2 = oracle.from_f64(back[i:i + 1])
             assert same_bits(h2, hi[i:i + 1]) and same_bits(l2, lo[i:i + 1]), i
     assert checked > 10000
+
+
+# Values outside the float-float range: the documented operation sequence
+# still fixes every word (IEEE binary32/binary64 rules), though the pairs are
+# not float-float numbers.
+_FMAX = float(np.finfo(np.float32).max)
+_THRESH = _FMAX + 2.0 ** 103          # binary32 overflow threshold (ties to even: inf)
+
+
+def _special_inputs():
+    return np.array([np.inf, -np.inf, np.nan, _FMAX, -_FMAX, _THRESH, -_THRESH,
+                     np.nextafter(_THRESH, 0.0), 1e39, -1e300, 0.0, -0.0, 5e-324, 1e-46],
+                    dtype=np.float64)
+
+
+def test_from_f64_special_values_closed_forms():
+    x = _special_inputs()
+    hi, lo = oracle.from_f64(x)
+    inf = np.float32(np.inf)
+    # infinities: hi = x, lo = fl32(inf - inf) = NaN
+    assert hi[0] == inf and np.isnan(lo[0]) and hi[1] == -inf and np.isnan(lo[1])
+    assert np.isnan(hi[2]) and np.isnan(lo[2])
+    # FLT_MAX is a binary32 value: exact, lo = +0
+    assert hi[3] == np.float32(_FMAX) and lo[3] == 0 and not np.signbit(lo[3])
+    assert hi[4] == -np.float32(_FMAX) and lo[4] == 0
+    # at the overflow threshold hi rounds to inf and lo = fl32(x - inf) = -inf
+    assert hi[5] == inf and lo[5] == -inf and hi[6] == -inf and lo[6] == inf
+    # just below it hi = FLT_MAX and lo = fl32(x - FLT_MAX) = fl32(2^103 - 2^75)
+    # = 2^103: a valid pair within 2^-48 |x| (here 2^-53) of x
+    assert hi[7] == np.float32(_FMAX) and lo[7] == np.float32(2.0 ** 103)
+    xi = Fraction(float(x[7]))
+    assert abs(frac(hi[7]) + frac(lo[7]) - xi) <= Fraction(1, 1 << 48) * xi
+    assert hi[8] == inf and lo[8] == -inf and hi[9] == -inf and lo[9] == inf
+    # signed zeros: hi keeps the sign, lo = fl32(x - hi) = +0
+    assert hi[10] == 0 and not np.signbit(hi[10]) and lo[10] == 0 and not np.signbit(lo[10])
+    assert hi[11] == 0 and np.signbit(hi[11]) and lo[11] == 0 and not np.signbit(lo[11])
+    # below half the smallest binary32 subnormal: hi = 0, lo = fl32(x) = 0
+    assert hi[12] == 0 and lo[12] == 0 and hi[13] == 0 and lo[13] == 0
+
+
+def test_to_f64_special_pairs_closed_forms():
+    inf, nan = np.float32(np.inf), np.float32(np.nan)
+    hi = np.array([inf, inf, -inf, nan, inf, np.float32(_FMAX), 0.0], np.float32)
+    lo = np.array([0.0, nan, inf, 1.0, -inf, np.float32(_FMAX), -0.0], np.float32)
+    x = oracle.to_f64(hi, lo)
+    assert x[0] == np.inf and np.isnan(x[1]) and np.isnan(x[2]) and np.isnan(x[3])
+    assert np.isnan(x[4])
+    assert x[5] == 2.0 * _FMAX                      # finite in binary64
+    assert x[6] == 0 and not np.signbit(x[6])       # +0 + -0 = +0
