@@ -144,6 +144,48 @@ def test_special_values_match_the_oracle(op, n):
     assert_parity(op, a, b, gpu_op(op, a, b), f"specials n={n}")
 
 
+def test_concurrent_host_threads_on_separate_streams():
+    # the entry points keep no mutable global state: four host threads, each
+    # with its own stream and data, issue the operators at the same time (the
+    # foreign calls release the interpreter lock); every result is the oracle's
+    import threading
+    _announce("[gpu] elementwise from four host threads on four streams")
+    ff = _ff()
+    n = (1 << 20) + 5
+    jobs = []
+    for k in range(4):
+        a, b, _ = fi.mixed_ff_pair(n, 3300 + k)
+        jobs.append((a, b, a.cuda(), b.cuda(), torch.cuda.Stream()))
+    torch.cuda.synchronize()
+    results = [dict() for _ in jobs]
+    errors = []
+    fns = {"add": ff.ff_add, "mul": ff.ff_mul, "div": ff.ff_div,
+           "add_accurate": ff.ff_add_accurate}
+
+    def work(k):
+        try:
+            _, _, ad, bd, st = jobs[k]
+            with torch.cuda.stream(st):
+                for rep in range(20):
+                    for op in ("add", "mul", "div", "add_accurate"):
+                        results[k][op] = fns[op](ad, bd, stream=st)
+            st.synchronize()
+        except Exception as exc:   # surfaced in the main thread
+            errors.append(exc)
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for k, (a, b, _, _, _) in enumerate(jobs):
+        for op, got in results[k].items():
+            g = got.cpu().numpy()
+            rh, rl = oracle.elementwise(op, a[0].numpy(), a[1].numpy(), b[0].numpy(), b[1].numpy())
+            assert same_bits(g[0], rh) and same_bits(g[1], rl), (k, op)
+
+
 def test_zero_length_is_a_noop():
     a = torch.empty(2, 0, device="cuda")
     r = gpu_op("add", a, a)
