@@ -34,6 +34,10 @@
  *           it; elementwise results are therefore reproducible bit for bit.
  * Threads   Entry points hold no mutable global state and may be called from
  *           several host threads.
+ * Graphs    Every entry point except ff_dot_batched_autotune only enqueues
+ *           kernels: no allocation, no memset, no host wait.  A sequence of
+ *           calls can therefore be captured into a HIP graph and replayed;
+ *           workspaces and outputs are then bound at capture time.
  */
 #ifndef FF_H
 #define FF_H
