@@ -334,13 +334,18 @@ __global__ __launch_bounds__(256) void matvec_bwd_plain_da(
     dAl[i * ldda + j] = l;
 }
 
-// Dot backward: dx_i = Mul22(g, y_i), dy_i = Mul22(g, x_i).
 // Backward pass of the single float-float dot s = sum x_i y_i for one
-// upstream gradient g: dx_i = Mul22(g, y_i), dy_i = Mul22(g, x_i).  The
-// access pattern of the batched form below (one workgroup per block of 4096
-// elements in order; a thread loads all its 16 lane-contiguous elements
-// first, then computes and stores).
-__global__ __launch_bounds__(256) void dot_backward(const float *__restrict__ g_hi,
+// upstream gradient g: dx_i = Mul22(g, y_i), dy_i = Mul22(g, x_i).  One
+// workgroup of kDotBwdThreads per block of kDotBwdThreads * kDotBwdPer
+// consecutive elements, in launch order; a thread loads all its
+// lane-contiguous elements first, then computes and stores.  This shape
+// (that of the elementwise operators) measured 3 % faster than 256 threads
+// by 16 elements at 438.9 M elements; unlike the batched form, no block
+// pays a per-block set-up, so small blocks cost nothing extra.
+constexpr int kDotBwdThreads = 1024;
+constexpr int kDotBwdPer = 2;
+
+__global__ __launch_bounds__(kDotBwdThreads) void dot_backward(const float *__restrict__ g_hi,
                                                     const float *__restrict__ g_lo,
                                                     const float *__restrict__ xh,
                                                     const float *__restrict__ xl,
@@ -351,14 +356,14 @@ __global__ __launch_bounds__(256) void dot_backward(const float *__restrict__ g_
                                                     float *__restrict__ dyh,
                                                     float *__restrict__ dyl, int64_t n)
 {
-    constexpr int kPer = 16;
+    constexpr int kPer = kDotBwdPer;
     const float gh = g_hi[0], gl = g_lo[0];
-    const int64_t b0 = static_cast<int64_t>(blockIdx.x) * (256 * kPer) + threadIdx.x;
+    const int64_t b0 = static_cast<int64_t>(blockIdx.x) * (kDotBwdThreads * kPer) + threadIdx.x;
     const bool want_dx = dxh != nullptr, want_dy = dyh != nullptr;
     float ox[kPer], oxl[kPer], oy[kPer], oyl[kPer];
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-        const int64_t i = b0 + 256 * k;
+        const int64_t i = b0 + static_cast<int64_t>(kDotBwdThreads) * k;
         const bool in = i < n;
         ox[k] = (want_dy && in) ? xh[i] : 0.0f;
         oxl[k] = (want_dy && in) ? xl[i] : 0.0f;
@@ -367,7 +372,7 @@ __global__ __launch_bounds__(256) void dot_backward(const float *__restrict__ g_
     }
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
-        const int64_t i = b0 + 256 * k;
+        const int64_t i = b0 + static_cast<int64_t>(kDotBwdThreads) * k;
         if (i >= n)
             break;
         float h, l;
@@ -687,10 +692,10 @@ ff_status ff_dot_backward(const float *g_hi, const float *g_lo, const float *x_h
         return FF_ERR_NULL;
     if (!all_aligned({g_hi, g_lo, x_hi, x_lo, y_hi, y_lo, dx_hi, dx_lo, dy_hi, dy_lo}, 4))
         return FF_ERR_ALIGN;
-    const int64_t blocks = ffh::cdiv(n, 256 * 16);
+    const int64_t blocks = ffh::cdiv(n, int64_t(kDotBwdThreads) * kDotBwdPer);
     if (blocks > INT32_MAX)
         return FF_ERR_SIZE;
-    hipLaunchKernelGGL(dot_backward, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+    hipLaunchKernelGGL(dot_backward, dim3(static_cast<unsigned>(blocks)), dim3(kDotBwdThreads), 0,
                        ffh::as_stream(stream), g_hi, g_lo, x_hi, x_lo, y_hi, y_lo,
                        want_dx ? dx_hi : nullptr, dx_lo, want_dy ? dy_hi : nullptr, dy_lo, n);
     return ffh::launch_status();
