@@ -397,16 +397,18 @@ __global__ __launch_bounds__(kDotBwdThreads) void dot_backward(const float *__re
 // workgroup finds, by two binary searches over the (clamped) offsets, the
 // vectors owning its first and last element, and when that window holds
 // between one and kBwdWin vectors copies their offsets and gradients into
-// LDS.  Thread t then
-// takes elements b0 + t + 256 k (each wavefront access is 256 contiguous
-// bytes of a plane) in increasing order, advancing its own vector index as
-// they cross vector starts.  (A block spanning more vectors -- tiny vectors
-// -- looks them up in global memory.)  24 to 32 bytes per element and two
-// Mul22: HBM-bound.  Measured on MI355X, these 4-byte lane-contiguous
-// accesses outran one float4 group per lane by 1.6x for this pattern of two
-// inputs and four outputs.
-constexpr int kBwdThreads = 256;
-constexpr int kBwdPerThread = 16;
+// LDS.  Thread t then takes elements b0 + t + kBwdThreads k (each wavefront
+// access is 256 contiguous bytes of a plane) in increasing order, advancing
+// its own vector index as they cross vector starts.  (A block spanning more
+// vectors -- tiny vectors -- looks them up in global memory.)  24 to 32
+// bytes per element and two Mul22: HBM-bound.  Measured on MI355X at
+// 438.9 M elements: these 4-byte lane-contiguous accesses outran one float4
+// group per lane by 1.6x for this pattern of two inputs and four outputs,
+// and 512 threads by 8 elements outran 256 by 16 (the same 4096-element
+// block, so the same searches) by 3 %; smaller blocks lose more to the
+// per-block searches than their access pattern gains.
+constexpr int kBwdThreads = 512;
+constexpr int kBwdPerThread = 8;
 constexpr int64_t kBwdBlock = static_cast<int64_t>(kBwdThreads) * kBwdPerThread;  // 4096
 constexpr int kBwdWin = 256;
 
@@ -478,7 +480,7 @@ __global__ __launch_bounds__(kBwdThreads) void dot_batched_bwd(
                 return clamped_offset(offsets, w, total);
             }
         };
-        // all of this thread's operands first: sixteen independent loads
+        // all of this thread's operands first: kBwdPerThread independent loads
         // per plane in flight
         float ox[kBwdPerThread], oxl[kBwdPerThread], oy[kBwdPerThread], oyl[kBwdPerThread];
 #pragma unroll
