@@ -258,8 +258,10 @@ def test_matvec_validation():
     g = [28672, 32768]
     dA = [36864, 40960]
     dx = [45056, 49152]
+    # partial sums: one float2 per 128-row band and column
+    assert ff.lib.ff_matvec_backward_workspace_size(300, 4, 0) == 3 * 4 * 8
     need = ff.lib.ff_matvec_backward_workspace_size(100, 4, 0)
-    assert need == 2 * 4 * 8                                  # 2 bands x 4 columns x float2
+    assert need == 1 * 4 * 8
     assert ff.lib.ff_matvec_backward_workspace_size(100, 4, 1) == 0
     ws = 1 << 20
     assert bw(100, 4, *A, 4, *x, *g, *dA, 4, *dx, 0, ws, need - 1, None) == ERR_WS
