@@ -313,3 +313,21 @@ def test_gemm_validation_and_workspace():
     assert g(4, 4, 4, *P[:2], 4, *P[2:4], 4, *P[4:], 4, 2, None, need, None) == ERR_NULL
     assert g(4, 4, 4, *P[:2], 4, *P[2:4], 4, *P[4:], 4, 2, ws, need - 1, None) == ERR_WS
     assert g(4, 4, 4, *P[:2], 4, *P[2:4], 4, *P[4:], 4, 2, ws + 16, need, None) == ERR_ALIGN
+
+
+def test_import_fails_loudly_without_the_library(tmp_path):
+    # a copy of the package without libff.so: the import itself must fail
+    # (no CPU fallback exists)
+    import shutil
+    import sys
+    src = os.path.dirname(ff.__file__)
+    dst = tmp_path / "paper_cs_0603115_amd"
+    dst.mkdir()
+    for name in os.listdir(src):
+        if name.endswith(".py"):
+            shutil.copy(os.path.join(src, name), dst / name)
+    r = subprocess.run([sys.executable, "-c", "import paper_cs_0603115_amd"], cwd=tmp_path,
+                       env={**os.environ, "PYTHONPATH": str(tmp_path)}, capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode != 0
+    assert "libff.so not found" in r.stderr
