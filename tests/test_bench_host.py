@@ -1,7 +1,8 @@
 """Host logic of the benchmark: the CPU baseline runs the unchanged oracle on
 disjoint pieces of one sample on several host threads; the pieces must give
 the same results as one call over the whole sample, and the piece bounds
-must tile the range.  Also: more than one GPU is refused with a message."""
+must tile the range.  Also: more than one GPU is refused with a message, and
+the defaults measure one GPU on the full 2^28-pair workload."""
 import subprocess
 import sys
 
@@ -86,3 +87,12 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in r.stderr
+
+
+def test_default_arguments_measure_one_gpu_on_the_full_workload():
+    a = bench.parse_args([])
+    assert a.gpus == 1 and a.steps > 0 and a.warmup >= 0
+    assert a.log2n == 28 and a.seed == 115002 and a.dot_cfg is None
+    assert not a.no_cpu_baseline and not a.no_secondary
+    b = bench.parse_args(["--steps", "5", "--warmup", "2", "--dot-cfg", "512,8192,4096,8"])
+    assert (b.steps, b.warmup, b.dot_cfg) == (5, 2, "512,8192,4096,8")
