@@ -92,7 +92,7 @@ def parse_args(argv=None):
                    help="block,chunk,grid,unroll of the batched dot; skips the autotuner "
                         "(so that a profile holds only launches of this shape)")
     p.add_argument("--no-secondary", action="store_true",
-                   help="skip the batched-dot, GEMM and matvec measurements")
+                   help="skip the batched-dot, Horner, GEMM, matvec and conversion measurements")
     return p.parse_args(argv)
 
 
@@ -389,6 +389,22 @@ def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
             f"pieces, C oracle on {th} host threads, {dtp:.2f} s ({dt:.2f} s on one)")
     out["matvec_8192"] = mv
     del A, xv, g
+    torch.cuda.empty_cache()
+
+    n = 1 << 28
+    log("[bench] binary64 <-> float-float conversions at N = 2^28")
+    xd = fi.gaussian_f32((n,), 115051, device=dev).double()
+    pair = ff.ff_empty((n,), device=dev)
+    back = torch.empty_like(xd)
+    conv = {}
+    for name, fn in (("from_f64", lambda: ff.ff_from_f64(xd, out=pair, stream=stream)),
+                     ("to_f64", lambda: ff.ff_to_f64(pair, out=back, stream=stream))):
+        ms = _time_launches(fn, 10, stream, warmup=2)
+        gbs = 16 * n / (ms * 1e-3) / 1e9                # 8 B read + 8 B written per element
+        conv[name] = {"ms": round(ms, 4), "GB/s": round(gbs, 1),
+                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out["conversions_2p28"] = conv
+    del xd, pair, back
     torch.cuda.empty_cache()
     return out
 

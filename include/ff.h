@@ -516,8 +516,8 @@ ff_status ff_horner_ff(const float *coef_hi, const float *coef_lo,
  * ff_to_f64: x_i = (double) hi_i + (double) lo_i, one binary64 rounding
  *   (exact whenever the pair's bits fit in 53).
  * Pointers: device, caller-owned; binary64 plane 8-byte aligned, binary32
- * planes 4-byte aligned (16-byte alignment of all three selects the
- * four-per-lane path).  No aliasing between the binary64 and binary32 planes.
+ * planes 4-byte aligned.  No aliasing between the binary64 and binary32
+ * planes.
  * Errors: FF_ERR_SIZE (n < 0), FF_ERR_NULL, FF_ERR_ALIGN, FF_ERR_HIP.
  * n = 0 is a no-op. */
 ff_status ff_from_f64(const double *x, float *hi, float *lo, int64_t n,

@@ -1,8 +1,8 @@
 """GPU parity of the binary64 <-> float-float conversions: every word bit
 for bit against the oracle, on wide exponent ranges (low words down to the
-subnormal range, signed zeros), ragged sizes, unaligned planes (the
-one-per-lane kernel) and a 2^24-element run; infinities, NaN and values
-beyond the binary32 range on both launch forms; the Python short names are
+subnormal range, signed zeros), ragged sizes, planes aligned to 4 or 8 bytes
+only and a 2^24-element run; infinities, NaN and values beyond the binary32
+range on 16-byte aligned and unaligned planes; the Python short names are
 the same entry points."""
 import sys
 
@@ -81,7 +81,7 @@ def _same_or_both_nan(a, b, view):
 def test_special_values_match_the_oracle(vec):
     # infinities, NaN, FLT_MAX, the binary32 overflow threshold and its
     # neighbour, finite values beyond binary32, signed zeros, values below the
-    # smallest subnormal, on both launch forms (float4 groups when aligned)
+    # smallest subnormal, on 16-byte aligned and on merely 4/8-byte aligned planes
     print(f"[gpu] conversions of special values (vec={vec})", file=sys.stderr, flush=True)
     ff = _ff()
     fmax = float(np.finfo(np.float32).max)
@@ -89,7 +89,7 @@ def test_special_values_match_the_oracle(vec):
     base = np.array([np.inf, -np.inf, np.nan, fmax, -fmax, thresh, -thresh,
                      np.nextafter(thresh, 0.0), 1e39, -1e300, 0.0, -0.0, 5e-324, 1e-46,
                      1e-40, -3e-39], dtype=np.float64)
-    x = np.tile(base, 9)                                   # 144 values: whole float4 groups
+    x = np.tile(base, 9)                                   # 144 values
     xd = torch.from_numpy(x).cuda() if vec else torch.from_numpy(np.r_[0.0, x]).cuda()[1:]
     got = ff.ff_from_f64(xd) if vec else ff.ff_from_f64(
         xd, out=ff.ff_zeros((x.size + 1,), device="cuda")[:, 1:])
