@@ -545,9 +545,10 @@ def main(argv=None) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32x2 (float-float: binary32 hi + lo)",
+        "dtype": "f32",
         "data": "synthetic (seeded; 65% base +-2^U[-20,20], 25% cancellation, 10% exponent gap)",
         "config": {"workload": f"elementwise ff add/sub/mul/div on N=2^{args.log2n} SoA hi/lo pairs",
+                   "format": "float-float: binary32 hi + lo, computed in binary32 arithmetic",
                    "n": n, "ops_per_step": 4, "seed": args.seed},
         "roofline": {
             "bound": "hbm",
