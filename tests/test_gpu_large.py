@@ -12,7 +12,10 @@ holds these comfortably; each case frees its tensors before the next.
 * sliced GEMM (int8 digits) with A of 65536 x 32800 (> 2^31 entries, K split
   into chunks): sampled entries within 2^-44 (|A||B|) of the exact product;
 * compensated Horner and the binary64 conversions at 2^31 + 5 points:
-  bit-exact on the tail, the 2^31 window and a strided sample.
+  bit-exact on the tail, the 2^31 window and a strided sample;
+* the batched dot backward over a vector of 2^31 + 3 ones (plus elements
+  outside every vector) and the single-dot backward at 2^31 + 9: every
+  sampled gradient word equals its closed form (Mul22(g, 1) = g).
 """
 import sys
 from fractions import Fraction
@@ -163,3 +166,42 @@ def test_horner_and_conversions_beyond_2p31():
     hi, lo = oracle.from_f64(xds)
     assert same_bits(ps[0], hi) and same_bits(ps[1], lo)
     assert np.array_equal(bs.view(np.uint64), oracle.to_f64(hi, lo).view(np.uint64))
+
+
+def test_dot_backward_beyond_2p31():
+    # x = y = 1: Mul22(g, (1, 0)) = g exactly, so every gradient word is a
+    # closed form; the batched form gives each vector's own g and zeros
+    # outside all vectors
+    lengths = [5, BIG + 3, 7]
+    lead, trail = 2, 3
+    total = lead + sum(lengths) + trail
+    _announce(f"[gpu] large: batched dot backward, total {total}")
+    ff = _ff()
+    offs_h = np.concatenate([[lead], lead + np.cumsum(lengths)]).astype(np.int64)
+    x = torch.ones(total, device="cuda")
+    g = torch.tensor([[1.5, -2.0, 0.75], [2.0 ** -30, 2.0 ** -31, -(2.0 ** -27)]], device="cuda")
+    dx, dy = ff.ff_dot_batched_backward(g, x, x, torch.from_numpy(offs_h).cuda())
+    idx = _sample_index(total, "cuda")
+    dxs, dys = dx[:, idx].cpu().numpy(), dy[:, idx].cpu().numpy()
+    del dx, dy
+    _free()
+    owner = np.searchsorted(offs_h, idx.cpu().numpy(), side="right") - 1
+    gn = g.cpu().numpy()
+    for k, v in enumerate(owner):
+        want = gn[:, v] if 0 <= v < len(lengths) else np.zeros(2, np.float32)
+        assert np.array_equal(dxs[:, k], want) and np.array_equal(dys[:, k], want), (k, v)
+    # the single-dot backward over float-float inputs of the same length
+    n = BIG + 9
+    _announce(f"[gpu] large: dot backward, n {n}")
+    del x
+    _free()
+    xf = torch.zeros((2, n), device="cuda")
+    xf[0].fill_(1.0)
+    g1 = torch.tensor([-3.25, 2.0 ** -29], device="cuda")
+    dx, dy = ff.ff_dot_backward(g1, xf, xf)
+    idx = _sample_index(n, "cuda")
+    dxs, dys = dx[:, idx].cpu().numpy(), dy[:, idx].cpu().numpy()
+    del dx, dy, xf
+    _free()
+    want = g1.cpu().numpy()[:, None]
+    assert np.all(dxs == want) and np.all(dys == want)
