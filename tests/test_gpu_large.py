@@ -15,7 +15,9 @@ holds these comfortably; each case frees its tensors before the next.
   bit-exact on the tail, the 2^31 window and a strided sample;
 * the batched dot backward over a vector of 2^31 + 3 ones (plus elements
   outside every vector) and the single-dot backward at 2^31 + 9: every
-  sampled gradient word equals its closed form (Mul22(g, 1) = g).
+  sampled gradient word equals its closed form (Mul22(g, 1) = g);
+* the paper's Add12 stream operator and the copy probe at 2^31 + 11
+  elements (closed forms).
 """
 import sys
 from fractions import Fraction
@@ -205,3 +207,26 @@ def test_dot_backward_beyond_2p31():
     _free()
     want = g1.cpu().numpy()[:, None]
     assert np.all(dxs == want) and np.all(dys == want)
+
+
+def test_stream_operators_and_copy_beyond_2p31():
+    # Add12 of a = 1 + k 2^-10 (k = i mod 1024) and b = 2^-30: s = a exactly
+    # (b is below half an ulp of a), r = b; the copy probe on the same data
+    n = BIG + 11
+    _announce(f"[gpu] large: Add12 and the copy probe at n={n}")
+    ff = _ff()
+    a = (torch.arange(n, device="cuda", dtype=torch.int64) % 1024).to(torch.float32)
+    a.mul_(2.0 ** -10).add_(1.0)
+    b = torch.full((n,), 2.0 ** -30, device="cuda")
+    out = ff.ff_add12(a, b)
+    idx = _sample_index(n, "cuda")
+    outs, as_ = out[:, idx].cpu().numpy(), a[idx].cpu().numpy()
+    del out, b
+    _free()
+    assert np.array_equal(outs[0], as_) and np.all(outs[1] == np.float32(2.0 ** -30))
+    dst = torch.empty_like(a)
+    ff.ff_copy(a, dst)
+    ds = dst[idx].cpu().numpy()
+    del a, dst
+    _free()
+    assert np.array_equal(ds, as_)
