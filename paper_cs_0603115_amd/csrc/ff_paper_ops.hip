@@ -5,19 +5,19 @@
 //   Mul12 with FMA TwoProd or with Dekker's Split (Mul12 theorem),
 //   binary32 add, multiply and multiply-add (one rounding).
 //
-// Same streaming structure as the float-float operators: 1024-thread
-// workgroups in launch order, two lane-contiguous elements per thread and
-// plane, all 4-byte non-temporal loads issued before the arithmetic (plane
-// by plane where the kernel writes two planes), any
-// 4-byte alignment; one float4 group per plane and thread below 2^22
-// elements.  Bytes per element: 12 (add, mul), 16 (mad, Add12,
-// Mul12); all HBM-bound at large n, launch-bound at the paper's sizes.
+// Same streaming structure as the float-float operators: workgroups in
+// launch order, lane-contiguous elements (1024 threads by 2 per plane for the
+// kernels with two output planes, 256 by 4 for those with one), all 4-byte
+// non-temporal loads issued before the arithmetic (plane by plane where the
+// kernel writes two planes), any 4-byte alignment; one float4 group per plane
+// and thread below 2^22 elements.  Bytes per element: 12 (add, mul), 16 (mad,
+// Add12, Mul12); all HBM-bound at large n, launch-bound at the paper's sizes.
 #include "ff_device.h"
 #include "ff_host.h"
 
 namespace ffk {
 
-constexpr int kStreamBlock = 1024;
+constexpr int kStreamBlock = 1024;   // workgroup of the float4 form (below 2^22)
 
 // An operator maps IN binary32 inputs of one element to OUT outputs.
 struct OpAdd12 {
@@ -98,15 +98,25 @@ __global__ __launch_bounds__(kStreamBlock) void stream_vec(StreamPlanes<Op::kIn,
         __builtin_nontemporal_store(y[k], reinterpret_cast<f32x4 *>(p.out[k]) + g);
 }
 
-constexpr int kStreamPer = 2;   // elements.per thread per plane
-constexpr int64_t kStreamSpan = static_cast<int64_t>(kStreamBlock) * kStreamPer;
+// Launch shape of the lane-contiguous form, by the number of output planes
+// (measured at N = 2^28): two outputs (Add12, Mul12) stream fastest with
+// 1024 threads by 2 elements, the elementwise operators' shape; one output
+// (binary32 Add, Mul, Mad) with 256 threads by 4 elements, 5-13 % faster
+// there (Add: 0.49 against 0.56 ms, 6.5 TB/s).
+template <class Op>
+struct StreamShape {
+    static constexpr int kBlock = Op::kOut >= 2 ? 1024 : 256;
+    static constexpr int kPer = Op::kOut >= 2 ? 2 : 4;   // elements per thread per plane
+    static constexpr int64_t kSpan = static_cast<int64_t>(kBlock) * kPer;
+};
 
 template <class Op>
-__global__ __launch_bounds__(kStreamBlock) void stream_op_kernel(StreamPlanes<Op::kIn, Op::kOut> p,
-                                                                 int64_t n)
+__global__ __launch_bounds__(StreamShape<Op>::kBlock) void stream_op_kernel(
+    StreamPlanes<Op::kIn, Op::kOut> p, int64_t n)
 {
-    const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kStreamSpan + threadIdx.x;
-    float x[kStreamPer][Op::kIn];
+    using Sh = StreamShape<Op>;
+    const int64_t b0 = static_cast<int64_t>(blockIdx.x) * Sh::kSpan + threadIdx.x;
+    float x[Sh::kPer][Op::kIn];
     // Every load is issued before any arithmetic.  Measured at N = 2^26 and
     // 2^28: with two output planes, issuing the loads one input plane at a
     // time is 1 % faster than element by element; with one output plane it
@@ -115,23 +125,23 @@ __global__ __launch_bounds__(kStreamBlock) void stream_op_kernel(StreamPlanes<Op
 #pragma unroll
         for (int q = 0; q < Op::kIn; ++q) {
 #pragma unroll
-            for (int k = 0; k < kStreamPer; ++k) {
-                const int64_t i = b0 + static_cast<int64_t>(kStreamBlock) * k;
+            for (int k = 0; k < Sh::kPer; ++k) {
+                const int64_t i = b0 + static_cast<int64_t>(Sh::kBlock) * k;
                 x[k][q] = i < n ? __builtin_nontemporal_load(p.in[q] + i) : 0.0f;
             }
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < kStreamPer; ++k) {
-            const int64_t i = b0 + static_cast<int64_t>(kStreamBlock) * k;
+        for (int k = 0; k < Sh::kPer; ++k) {
+            const int64_t i = b0 + static_cast<int64_t>(Sh::kBlock) * k;
 #pragma unroll
             for (int q = 0; q < Op::kIn; ++q)
                 x[k][q] = i < n ? __builtin_nontemporal_load(p.in[q] + i) : 0.0f;
         }
     }
 #pragma unroll
-    for (int k = 0; k < kStreamPer; ++k) {
-        const int64_t i = b0 + static_cast<int64_t>(kStreamBlock) * k;
+    for (int k = 0; k < Sh::kPer; ++k) {
+        const int64_t i = b0 + static_cast<int64_t>(Sh::kBlock) * k;
         if (i < n) {
             float y[Op::kOut];
             Op::apply(x[k], y);
@@ -182,11 +192,11 @@ ff_status stream_op(StreamPlanes<Op::kIn, Op::kOut> p, int64_t n, void *stream_p
             rest.in[k] += done;
         for (int k = 0; k < Op::kOut; ++k)
             rest.out[k] += done;
-        const int64_t blocks = ffh::cdiv(n - done, kStreamSpan);
+        const int64_t blocks = ffh::cdiv(n - done, StreamShape<Op>::kSpan);
         if (blocks > INT32_MAX)
             return FF_ERR_SIZE;
         hipLaunchKernelGGL(stream_op_kernel<Op>, dim3(static_cast<unsigned>(blocks)),
-                           dim3(kStreamBlock), 0, st, rest, n - done);
+                           dim3(StreamShape<Op>::kBlock), 0, st, rest, n - done);
     }
     return ffh::launch_status();
 }
