@@ -499,10 +499,10 @@ def main(argv=None) -> int:
 
     kernel_ms = {op: sum(s.elapsed_time(e) for s, e in events[op]) / args.steps for op in OPS}
 
-    # Bandwidth reference: the ff_copy probe (one plane in, one out; one
-    # float4 group per lane, 16-byte non-temporal loads and stores, the
-    # fastest copy pattern measured) over N binary32 words, after the timed
-    # region.  It also calibrates the HBM byte counters.
+    # Bandwidth reference: the ff_copy probe (one plane in, one out; 512
+    # threads by 4 lane-contiguous elements, non-temporal, the fastest copy
+    # pattern measured) over N binary32 words, after the timed region.  It
+    # also calibrates the HBM byte counters.
     copy_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(args.steps)]
     for s_ev, e_ev in copy_ev:

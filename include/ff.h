@@ -530,10 +530,10 @@ ff_status ff_to_f64(const float *hi, const float *lo, double *x, int64_t n,
 /* ------------------------------------------------------------------------ */
 
 /* dst[i] = src[i] for i < n (binary32): the streaming reference for the
- * roofline and the HBM counter calibration.  One float4 group per lane with
- * non-temporal loads and stores when both pointers are 16-byte aligned (the
- * fastest copy measured on MI355X), 4-byte accesses for the tail and
- * otherwise.  Errors as for the elementwise operators. */
+ * roofline and the HBM counter calibration.  512 threads by 4
+ * lane-contiguous elements with non-temporal 4-byte loads and stores, any
+ * 4-byte alignment: the fastest copy measured on MI355X.  Errors as for the
+ * elementwise operators. */
 ff_status ff_copy(const float *src, float *dst, int64_t n, void *stream);
 
 #ifdef __cplusplus
