@@ -288,6 +288,24 @@ def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
     msb = _time_launches(dot_bwd, 10, stream)
     gbsb = 24 * total / (msb * 1e-3) / 1e9
     del dxb, dyb, gvec
+    # the other entry points of the family on the same batch and launch shape:
+    # float-float inputs (16 B per element), sums of binary32 (4 B) and of
+    # float-float (8 B) terms
+    xf = torch.stack([x, torch.zeros_like(x)])
+    yf = torch.stack([y, torch.zeros_like(y)])
+    family = {}
+    for name, fn, bpe in (
+            ("dot_ff_inputs", lambda: ff.ff_dot_ff_batched(xf, yf, offs, cfg=cfg, out=res,
+                                                           workspace=ws, stream=stream), 16),
+            ("sum_f32", lambda: ff.ff_sum_batched(x, offs, cfg=cfg, out=res, workspace=ws,
+                                                  stream=stream), 4),
+            ("sum_ff", lambda: ff.ff_sum_ff_batched(xf, offs, cfg=cfg, out=res, workspace=ws,
+                                                    stream=stream), 8)):
+        msf = _time_launches(fn, 10, stream)
+        gbf = bpe * total / (msf * 1e-3) / 1e9
+        family[name] = {"ms": round(msf, 4), "GB/s": round(gbf, 1),
+                        "hbm_frac": round(gbf / HBM_PEAK_GBS, 4), "bytes_per_element": bpe}
+    del xf, yf
     out["dot_batched"] = {"elements": total, "ms": round(ms, 4), "elements/s": total / (ms * 1e-3),
                           "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                           "cfg": list(cfg),
@@ -295,7 +313,8 @@ def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
                                                "hbm_frac": round(gbs2 / HBM_PEAK_GBS, 4)},
                           "backward": {"ms": round(msb, 4), "GB/s": round(gbsb, 1),
                                        "hbm_frac": round(gbsb / HBM_PEAK_GBS, 4),
-                                       "bytes_per_element": 24}}
+                                       "bytes_per_element": 24},
+                          "family": family}
     if cpu:
         import oracle
         offs_h = offs.cpu().numpy()
