@@ -75,31 +75,34 @@ static void fast_add12(float a, float b, float *s_out, float *r_out)
     *r_out = b - z;
 }
 
-/* Split theorem (Dekker): p = 24, splitting point s = 12, constant 2^12 + 1. */
+/* Split theorem (Dekker, after Veltkamp): for p = 24 and the splitting
+ * point 12, scaling by 2^12 + 1 and cancelling the scaled value against
+ * itself leaves the upper 12 significant bits of a; the remainder a - hi
+ * then fits in the other 12 bits (sign included) and is exact. */
 static void split(float a, float *hi_out, float *lo_out)
 {
     const float c_split = 4097.0f; /* 2^12 (+) 1, exact */
-    float c = c_split * a;
-    float a_big = c - a;
-    float a_hi = c - a_big;
-    float a_lo = a - a_hi;
-    *hi_out = a_hi;
-    *lo_out = a_lo;
+    const float scaled = c_split * a;
+    const float hi = scaled - (scaled - a);
+    *hi_out = hi;
+    *lo_out = a - hi;
 }
 
-/* Mul12 theorem (Dekker): x = a (x) b and the error y, with a*b = x + y. */
+/* Mul12 theorem (Dekker's exact product): with a and b split in halves,
+ * the four half products are exact, so peeling them off the rounded product
+ * x one by one (largest first) leaves the rounding error -y exactly; the
+ * last half product then gives y with a*b = x + y. */
 static void mul12_dekker(float a, float b, float *x_out, float *y_out)
 {
-    float x = a * b;
-    float ah, al, bh, bl;
-    split(a, &ah, &al);
-    split(b, &bh, &bl);
-    float err1 = x - (ah * bh);
-    float err2 = err1 - (al * bh);
-    float err3 = err2 - (ah * bl);
-    float y = (al * bl) - err3;
+    const float x = a * b;
+    float a1, a2, b1, b2; /* a = a1 + a2, b = b1 + b2, 12 bits each */
+    split(a, &a1, &a2);
+    split(b, &b1, &b2);
+    float rem = x - (a1 * b1);
+    rem = rem - (a2 * b1);
+    rem = rem - (a1 * b2);
     *x_out = x;
-    *y_out = y;
+    *y_out = (a2 * b2) - rem;
 }
 
 /* TwoProd with one fused multiply-add (not in the paper; same contract as

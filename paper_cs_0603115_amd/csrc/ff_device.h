@@ -25,26 +25,29 @@ __device__ __forceinline__ void add12(float a, float b, float &s, float &r)
     r = (a - (s - v)) + (b - v);
 }
 
-// Split theorem (Dekker) with p = 24, s = 12: a = hi + lo, 12 + 12 bits.
+// Split theorem (Dekker, after Veltkamp), p = 24 and splitting point 12:
+// the product with 2^12 + 1, cancelled against itself, keeps the upper 12
+// significant bits of a; the remainder fits in the lower 12 and is exact.
 __device__ __forceinline__ void split(float a, float &hi, float &lo)
 {
-    const float c = 4097.0f * a;
-    const float big = c - a;
-    hi = c - big;
+    const float scaled = 4097.0f * a;
+    hi = scaled - (scaled - a);
     lo = a - hi;
 }
 
-// Mul12 theorem (Dekker): x = a (x) b and y = a*b - x via Split.
+// Mul12 theorem (Dekker's exact product): the four products of the halves
+// are exact, so removing three of them from the rounded product x, largest
+// first, leaves minus the rounding error exactly; the fourth gives y.
 __device__ __forceinline__ void mul12_dekker(float a, float b, float &x, float &y)
 {
     x = a * b;
-    float ah, al, bh, bl;
-    split(a, ah, al);
-    split(b, bh, bl);
-    const float e1 = x - (ah * bh);
-    const float e2 = e1 - (al * bh);
-    const float e3 = e2 - (ah * bl);
-    y = (al * bl) - e3;
+    float a1, a2, b1, b2;
+    split(a, a1, a2);
+    split(b, b1, b2);
+    float rem = x - (a1 * b1);
+    rem = rem - (a2 * b1);
+    rem = rem - (a1 * b2);
+    y = (a2 * b2) - rem;
 }
 
 // TwoProd with one fused multiply-add (v_fma_f32): the same pair as Mul12

@@ -35,6 +35,9 @@ def _run(op, ins):
         return oracle.split(*a)
     if op == "mul12":
         return oracle.mul12(*a)
+    if op == "horner_comp":
+        # coefficients a0 .. an, then the point x
+        return [oracle.horner_comp(np.concatenate(a[:-1]), a[-1])]
     return oracle.elementwise({"add22": "add", "mul22": "mul", "div22": "div"}.get(op, op), *a)
 
 
@@ -46,8 +49,17 @@ def test_hand_derived_case(row):
     op, ins, outs, why = row
     got = _run(op, [_f(w) for w in ins.split()])
     want = [_f(w) for w in outs.split()]
+    assert len(got) == len(want), (op, why)
     for g, w in zip(got, want):
         assert g[0].view(np.uint32) == w.view(np.uint32), (op, why, g[0], w)
+
+
+def check_hand_cases(op: str) -> None:
+    """Every hand-derived case of one operator (used by the mutation tests)."""
+    rows = [r for r in HAND if r[0] == op]
+    assert rows, op
+    for row in rows:
+        test_hand_derived_case(row)
 
 
 def test_oracle_regression_lock():

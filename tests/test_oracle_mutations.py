@@ -17,6 +17,7 @@ import test_oracle_accurate_mul_div as AMD
 import test_oracle_compensated as CMP
 import test_oracle_convert as CNV
 import test_oracle_dot_backward as DBW
+import test_oracle_golden as GOLD
 import test_oracle_horner as HOR
 import test_oracle_paper_tables as TAB
 import test_oracle_primitives as PRIM
@@ -101,16 +102,40 @@ CMP_PINS = [
     lambda: CMP.test_sum2_error_bound_random(3000),
 ]
 
+# Evaluation-order pins: the hand-derived cases whose results change when a
+# chain is regrouped (the regression lock, written by the oracle itself, is
+# deliberately not among them).
+ORDER_PINS = {op: [lambda op=op: GOLD.check_hand_cases(op)]
+              for op in ("add22", "mul22", "div22", "horner_comp")}
+
 # (name, original text, planted text, pins expected to catch it)
 MUTATIONS = [
+    ("add22_order_first_arm", "s = (((ah - r) + bh) + bl) + al;",
+     "s = (((ah - r) + bh) + al) + bl;", ORDER_PINS["add22"]),
+    ("add22_order_second_arm", "s = (((bh - r) + ah) + al) + bl;",
+     "s = (((bh - r) + ah) + bl) + al;", ORDER_PINS["add22"]),
+    ("mul22_order_t2_first", "float t3 = ((ah * bl) + (al * bh)) + t2;",
+     "float t3 = (t2 + (ah * bl)) + (al * bh);", ORDER_PINS["mul22"]),
+    ("mul22_order_t2_with_al_bh", "float t3 = ((ah * bl) + (al * bh)) + t2;",
+     "float t3 = (t2 + (al * bh)) + (ah * bl);", ORDER_PINS["mul22"]),
+    ("div22_order_al_before_uu", "float t = (((ah - u) - uu) + al) - (c * bl);",
+     "float t = (((ah - u) + al) - uu) - (c * bl);", ORDER_PINS["div22"]),
+    ("div22_order_u_plus_uu", "float t = (((ah - u) - uu) + al) - (c * bl);",
+     "float t = ((ah - (u + uu)) + al) - (c * bl);", ORDER_PINS["div22"]),
+    ("horner_comp_order_pi_first", "            r = (r * xk) + (pi + sigma);",
+     "            r = ((r * xk) + pi) + sigma;", ORDER_PINS["horner_comp"]),
+    ("horner_comp_order_sigma_first", "            r = (r * xk) + (pi + sigma);",
+     "            r = ((r * xk) + sigma) + pi;", ORDER_PINS["horner_comp"]),
     ("add12_error_sign", "float r = (a - (s - v)) + (b - v);",
      "float r = (a - (s - v)) - (b - v);", PRIM_PINS),
     ("add12_wrong_operand", "float v = s - a;", "float v = s - b;", PRIM_PINS),
     ("split_constant", "const float c_split = 4097.0f;", "const float c_split = 4096.0f;",
      PRIM_PINS),
-    ("split_low_word", "float a_lo = a - a_hi;", "float a_lo = a - a_big;", PRIM_PINS),
-    ("dekker_transposed_term", "float err2 = err1 - (al * bh);",
-     "float err2 = err1 - (ah * bl);", PRIM_PINS),
+    ("split_low_word", "    *lo_out = a - hi;", "    *lo_out = a - scaled;", PRIM_PINS),
+    ("split_uncancelled", "const float hi = scaled - (scaled - a);",
+     "const float hi = scaled - a;", PRIM_PINS),
+    ("dekker_transposed_term", "rem = rem - (a2 * b1);",
+     "rem = rem - (a1 * b2);", PRIM_PINS),
     ("fma_sign", "*y_out = fmaf(a, b, -x);", "*y_out = fmaf(a, b, x);", PRIM_PINS),
     ("add22_branch_flipped", "if (fabsf(ah) >= fabsf(bh))", "if (fabsf(ah) <= fabsf(bh))",
      OP_PINS),
