@@ -13,7 +13,9 @@
  *           example memory allocated by PyTorch on the current device).  The
  *           library never allocates, frees or retains device memory; scratch
  *           space, where needed, is a caller-provided workspace whose size is
- *           returned by the matching *_workspace_size() function.
+ *           returned by the matching *_workspace_size() function.  The one
+ *           exception is ff_dot_batched_noalloc, whose scratch is a static
+ *           device array of the library (see there).
  * Streams   `stream` is a hipStream_t passed as void*; NULL is the null
  *           stream.  Work is enqueued asynchronously on that stream, on the
  *           current HIP device, and is complete when the stream is.
@@ -32,8 +34,9 @@
  *           preserved and correctly rounded binary32 division, so that each
  *           operator performs exactly the operation sequence documented for
  *           it; elementwise results are therefore reproducible bit for bit.
- * Threads   Entry points hold no mutable global state and may be called from
- *           several host threads.
+ * Threads   Entry points hold no mutable global state (apart from the
+ *           per-device address of ff_dot_batched_noalloc's scratch) and may
+ *           be called from several host threads.
  * Graphs    Every entry point except ff_dot_batched_autotune only enqueues
  *           kernels: no allocation, no memset, no host wait.  A sequence of
  *           calls can therefore be captured into a HIP graph and replayed;
@@ -277,6 +280,30 @@ ff_status ff_sum2_batched(const float *x, const int64_t *offsets, int32_t nvec,
                           int64_t total_len, const ff_dot_cfg *cfg, void *ws,
                           size_t ws_bytes, float *out_hi, float *out_lo,
                           void *stream);
+
+/* Capacity of the static scratch array of ff_dot_batched_noalloc (bytes). */
+#define FF_NOALLOC_SCRATCH_BYTES ((size_t)4 << 20)
+
+/* ff_dot_batched without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same kernels, results (bit for bit for
+ * the same cfg), arguments and errors as ff_dot_batched; its scratch is a
+ * static device array of FF_NOALLOC_SCRATCH_BYTES inside the library, one
+ * copy per device, held until the process ends (its device address is looked
+ * up once per device on the first call there).  No allocation of any kind.
+ * Limit: the batch must satisfy ff_dot_batched_workspace_size(total_len,
+ * nvec, cfg) <= FF_NOALLOC_SCRATCH_BYTES, otherwise FF_ERR_WORKSPACE (with
+ * the default cfg, for example, 4096 vectors of up to 2.77e9 elements in
+ * all).  Nothing in the scratch needs to start at zero: every word a launch
+ * reads was written earlier in the same call.  Every call on one device
+ * shares that device's array, so calls that may overlap on one device (two
+ * streams, two host threads) race and give unspecified results; calls on
+ * one stream are ordered and safe.  Errors: those of ff_dot_batched, and
+ * FF_ERR_UNSUPPORTED for a device index of 64 or more. */
+ff_status ff_dot_batched_noalloc(const float *x, const float *y,
+                                 const int64_t *offsets, int32_t nvec,
+                                 int64_t total_len, const ff_dot_cfg *cfg,
+                                 float *out_hi, float *out_lo, void *stream);
 
 /* Launch-shape autotuner for ff_dot_batched on this batch: times every
  * candidate (block 256/512 x unroll 1/2/4/8 x chunk 1024..32768 x 2..16

@@ -25,7 +25,8 @@ __all__ = [
     "ff_add_accurate", "ff_sub_accurate", "ff_mul_accurate", "ff_div_accurate",
     "ff_add12", "ff_mul12", "f32_add", "f32_mul", "f32_mad",
     "ff_horner_f32", "ff_horner_comp", "ff_horner_ff",
-    "ff_dot_batched", "ff_dot_ff_batched", "ff_dot_batched_workspace_size",
+    "ff_dot_batched", "ff_dot_batched_noalloc", "ff_dot_ff_batched",
+    "ff_dot_batched_workspace_size",
     "ff_sum_batched", "ff_sum_ff_batched", "ff_dot2_batched", "ff_sum2_batched",
     "ff_matvec", "ff_matvec_backward", "ff_dot_backward", "ff_dot_batched_backward",
     "MATVEC_FAST", "MATVEC_PLAIN",
@@ -401,6 +402,29 @@ def ff_dot_batched(x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, cfg=
             ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
             ctypes.c_void_p(offsets.data_ptr()), nvec, x.numel(), _cfg_ptr(cfg),
             ctypes.c_void_p(ws.data_ptr()), ws.numel(), oh, ol, _stream_handle(stream)))
+    return out
+
+
+def ff_dot_batched_noalloc(x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, cfg=None,
+                           out=None, stream=None) -> torch.Tensor:
+    """ff_dot_batched through the entry point that takes no workspace (its
+    scratch is a static device array of the library, shared by every call on
+    the device: calls that may overlap there race).  Allocates the output
+    only when ``out`` is None."""
+    for t, name in ((x, "x"), (y, "y")):
+        if t.dtype != torch.float32 or t.dim() != 1 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError(f"{name}: contiguous float32 vector on a HIP device expected")
+    if x.numel() != y.numel():
+        raise ValueError("x and y differ in length")
+    nvec = _check_offsets(offsets, x.device)
+    out = ff_empty((nvec,), device=x.device) if out is None else out
+    _check_ff(out, "out")
+    oh, ol = _planes(out)
+    with torch.cuda.device(x.device):
+        check("ff_dot_batched_noalloc", lib.ff_dot_batched_noalloc(
+            ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+            ctypes.c_void_p(offsets.data_ptr()), nvec, x.numel(), _cfg_ptr(cfg), oh, ol,
+            _stream_handle(stream)))
     return out
 
 

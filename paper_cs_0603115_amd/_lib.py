@@ -63,6 +63,7 @@ SIGNATURES = {
     "ff_dot2_batched": ([_P, _P, _P, _i32, _i64, ctypes.POINTER(DotCfg), _P, _sz, _P, _P, _P],
                         _st),
     "ff_sum2_batched": ([_P, _P, _i32, _i64, ctypes.POINTER(DotCfg), _P, _sz, _P, _P, _P], _st),
+    "ff_dot_batched_noalloc": ([_P, _P, _P, _i32, _i64, ctypes.POINTER(DotCfg), _P, _P, _P], _st),
     "ff_dot_batched_autotune": ([_P, _P, _P, _i32, _i64, _P, _sz, _P, _P, _i32, _P,
                                  ctypes.POINTER(DotCfg), ctypes.POINTER(ctypes.c_float)], _st),
     "ff_matvec": ([_i64, _i64, _P, _P, _i64, _P, _P, _P, _P, _i32, _P], _st),

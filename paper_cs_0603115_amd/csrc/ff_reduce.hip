@@ -24,6 +24,8 @@
 //   ranges      int64x2[cap]     element range [s, e) of each chunk
 //   partials    float2[cap]      float-float partial of each chunk
 // with cap = total_len / chunk + nvec chunks at most.
+#include <atomic>
+
 #include "ff_device.h"
 #include "ff_host.h"
 
@@ -642,6 +644,80 @@ ff_status ff_sum2_batched(const float *x, const int64_t *offsets, int32_t nvec,
     return dot_batched_entry<InSumF32, AccComp>(InSumF32{x}, ffh::aligned(x, 16), offsets, nvec,
                                                 total_len, cfg, ws, ws_bytes, out_hi, out_lo,
                                                 stream);
+}
+
+} // extern "C"
+
+namespace {
+
+// Scratch memory of the allocation-free batched dot: a static device array,
+// one copy per device the library runs on, held until the process ends.
+// Host code never passes the array's name to a kernel (on the host it is
+// only a stand-in for the symbol): the device address is looked up once per
+// device with hipGetSymbolAddress and kept in `g_scratch_addr`.
+static __device__ __align__(256) unsigned char scratch[FF_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+std::atomic<void *> g_scratch_addr[kMaxScratchDevices];
+
+// Device address of `scratch` on the current device (looked up on the
+// first call on that device; a concurrent first call stores the same value).
+ff_status scratch_on_current_device(void **addr)
+{
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess)
+        return ffh::hip_failure(err);
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return FF_ERR_UNSUPPORTED;
+    void *p = g_scratch_addr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (err != hipSuccess)
+            return ffh::hip_failure(err);
+        if (!p)
+            return FF_ERR_HIP;
+        g_scratch_addr[dev].store(p, std::memory_order_release);
+    }
+    *addr = p;
+    return FF_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+ff_status ff_dot_batched_noalloc(const float *x, const float *y, const int64_t *offsets,
+                                 int32_t nvec, int64_t total_len, const ff_dot_cfg *cfg,
+                                 float *out_hi, float *out_lo, void *stream)
+{
+    // the argument checks of ff_dot_batched, in its order, plus the scratch
+    // limit, all before any HIP call
+    if (nvec < 0 || total_len < 0)
+        return FF_ERR_SIZE;
+    if (total_len > 0 && (!x || !y))
+        return FF_ERR_NULL;
+    if (!ffh::aligned(x, 4) || !ffh::aligned(y, 4))
+        return FF_ERR_ALIGN;
+    Cfg c;
+    const ff_status cs = resolve_cfg(cfg, c);
+    if (cs != FF_OK)
+        return cs;
+    if (nvec == 0)
+        return FF_OK;
+    if (!offsets || !out_hi || !out_lo)
+        return FF_ERR_NULL;
+    if (!ffh::aligned(offsets, 8) || !ffh::aligned(out_hi, 4) || !ffh::aligned(out_lo, 4))
+        return FF_ERR_ALIGN;
+    if (workspace_bytes(total_len, nvec, c.chunk) > FF_NOALLOC_SCRATCH_BYTES)
+        return FF_ERR_WORKSPACE;
+    void *ws = nullptr;
+    const ff_status ss = scratch_on_current_device(&ws);
+    if (ss != FF_OK)
+        return ss;
+    const bool vec = ffh::aligned(x, 16) && ffh::aligned(y, 16);
+    return dot_batched_entry(InF32{x, y}, vec, offsets, nvec, total_len, cfg, ws,
+                             FF_NOALLOC_SCRATCH_BYTES, out_hi, out_lo, stream);
 }
 
 ff_status ff_dot_batched_autotune(const float *x, const float *y, const int64_t *offsets,

@@ -243,6 +243,34 @@ def test_dot_validation(name):
     assert call(ws=ws + 64) == ERR_ALIGN
 
 
+def test_dot_noalloc_validation():
+    """The allocation-free batched dot checks its arguments, and its static
+    scratch limit, before any HIP call."""
+    fn = ff.lib.ff_dot_batched_noalloc
+    x, y, offs, oh, ol = 4096, 8192, 1 << 20, 2 << 20, 3 << 20
+
+    def call(x=x, y=y, offs=offs, nvec=8, total=1000, cfg=None, oh=oh, ol=ol):
+        cfgp = None if cfg is None else ctypes.byref(_lib.DotCfg(*cfg))
+        return fn(x, y, offs, nvec, total, cfgp, oh, ol, None)
+
+    assert call(nvec=-1) == ERR_SIZE
+    assert call(total=-5) == ERR_SIZE
+    assert call(nvec=0) == 0                           # nothing to do
+    assert call(cfg=(0, 0, 0, 3)) == ERR_ARG
+    assert call(x=None) == ERR_NULL
+    assert call(offs=None) == ERR_NULL
+    assert call(ol=None) == ERR_NULL
+    assert call(y=y + 2) == ERR_ALIGN
+    assert call(offs=offs + 4) == ERR_ALIGN
+    # the batch must fit the static scratch: 4 MiB
+    limit = 4 << 20
+    fits = ff.ff_dot_batched_workspace_size(2_773_499_903, 4096)
+    assert fits <= limit < ff.ff_dot_batched_workspace_size(2_773_499_904 + (1 << 14), 4096)
+    assert call(nvec=4096, total=(1 << 14) * (1 << 20)) == ERR_WS
+    assert call(nvec=300_000, total=1000) == ERR_WS   # too many vectors
+    assert call(nvec=8, total=1 << 40, cfg=(0, 64, 0, 0)) == ERR_WS
+
+
 def test_matvec_validation():
     mv = ff.lib.ff_matvec
     A = [4096, 8192]

@@ -1,0 +1,77 @@
+"""The allocation-free batched dot (static device scratch) against the
+workspace entry point it shares its kernels with.
+
+ff_dot_batched_noalloc runs the kernels of ff_dot_batched with the library's
+static scratch array instead of a caller workspace, so for the same launch
+shape its results must equal ff_dot_batched's bit for bit.  Two calls in a
+row, the second on a smaller batch, check that nothing from the first call's
+scratch contents leaks into the second; the first result is also held
+against the exact dot products of the oracle's long accumulator.
+"""
+import sys
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import torch
+
+import ff_inputs as fi
+import oracle
+from fpexact import frac
+
+pytestmark = pytest.mark.gpu
+
+
+def _ff():
+    import paper_cs_0603115_amd as ff
+    return ff
+
+
+def _bits(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def _both(ff, x, y, offs, cfg):
+    want = ff.ff_dot_batched(x, y, offs, cfg=cfg)
+    got = ff.ff_dot_batched_noalloc(x, y, offs, cfg=cfg)
+    torch.cuda.synchronize()
+    return want, got
+
+
+@pytest.mark.parametrize("cfg", [None, (256, 1024, 512, 2)], ids=["default", "small_chunks"])
+def test_noalloc_matches_workspace_entry_twice(cfg):
+    ff = _ff()
+    dev = torch.device("cuda:0")
+    print(f"[no_alloc] cfg={cfg}: 4096 vectors of 2^6..2^12", file=sys.stderr, flush=True)
+    x, y, offs = fi.batched_dot(7101, device=dev, nvec=4096, log2_min=6, log2_max=12)
+    want, got = _both(ff, x, y, offs, cfg)
+    assert np.array_equal(_bits(got), _bits(want))
+    # the first result against the exact values, within 2^-40 normwise
+    xs, ys, os_ = (t.cpu().numpy() for t in (x, y, offs))
+    exact = oracle.exact_dot_batched(xs, ys, os_)
+    absum = oracle.exact_dot_batched(np.abs(xs), np.abs(ys), os_)
+    g = got.cpu().numpy()
+    for v in range(0, 4096, 37):
+        assert abs(frac(g[0, v]) + frac(g[1, v]) - exact[v]) <= absum[v] * Fraction(1, 1 << 40)
+    # second call, smaller batch, unaligned planes (the element-wise path)
+    print(f"[no_alloc] cfg={cfg}: 37 vectors, unaligned", file=sys.stderr, flush=True)
+    x2, y2, offs2 = fi.batched_dot(7102, device=dev, nvec=38, log2_min=0, log2_max=11)
+    x2u, y2u = x2[1:], y2[1:]
+    offs2u = (offs2[:-1]).contiguous()
+    offs2u[-1] = x2u.numel()
+    want2, got2 = _both(ff, x2u, y2u, offs2u, cfg)
+    assert got2.shape == (2, 37)
+    assert np.array_equal(_bits(got2), _bits(want2))
+
+
+def test_noalloc_rejects_a_batch_beyond_the_scratch():
+    ff = _ff()
+    dev = torch.device("cuda:0")
+    x = torch.zeros(64, device=dev)
+    offs = torch.tensor([0, 64], dtype=torch.int64, device=dev)
+    out = ff.ff_empty((1,), device=dev)
+    # 2^40 elements claimed: the check refuses before anything is enqueued
+    status = ff.lib.ff_dot_batched_noalloc(
+        x.data_ptr(), x.data_ptr(), offs.data_ptr(), 1, 1 << 40, None,
+        out[0].data_ptr(), out[1].data_ptr(), None)
+    assert status == 4  # FF_ERR_WORKSPACE
