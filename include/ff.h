@@ -28,8 +28,12 @@
  * Alignment Float pointers must be 4-byte aligned (FF_ERR_ALIGN otherwise).
  *           Where an entry point has a float4 path for 16-byte aligned
  *           planes, its comment says when that path runs.
- * Aliasing  An output plane may be the same array as an input plane (in-place
- *           operation); partially overlapping arrays are undefined.
+ * Aliasing  Elementwise entry points (the float-float operators, ff_copy,
+ *           the paper's stream operators, the polynomial evaluators) allow
+ *           an output plane to be the same array as an input plane (in
+ *           place); partially overlapping arrays are undefined.  The outputs
+ *           of the reductions, products, matrix-vector products, backward
+ *           passes and conversions must not overlap any input.
  * Numerics  Device code is compiled with contraction off, binary32 denormals
  *           preserved and correctly rounded binary32 division, so that each
  *           operator performs exactly the operation sequence documented for

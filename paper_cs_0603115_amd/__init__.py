@@ -13,6 +13,8 @@ stream unless ``stream`` is given.
 from __future__ import annotations
 
 import ctypes
+import functools
+import inspect
 
 import torch
 
@@ -39,6 +41,30 @@ __all__ = [
 def build_info() -> str:
     """How the loaded library was built (target, numerics flags)."""
     return lib.ff_build_info().decode()
+
+
+def _torch_stream(stream):
+    if isinstance(stream, torch.cuda.Stream):
+        return stream
+    return torch.cuda.ExternalStream(int(stream))
+
+
+def _on_stream(fn):
+    """Run a wrapper with ``stream`` (when given) as torch's current stream,
+    so that the outputs and workspaces it allocates belong to the stream its
+    kernels are enqueued on: the caching allocator then cannot hand that
+    memory to other work before those kernels are done with it."""
+    sig = inspect.signature(fn)
+
+    @functools.wraps(fn)
+    def run(*args, **kwargs):
+        stream = sig.bind_partial(*args, **kwargs).arguments.get("stream")
+        if stream is None:
+            return fn(*args, **kwargs)
+        with torch.cuda.stream(_torch_stream(stream)):
+            return fn(*args, **kwargs)
+
+    return run
 
 
 def _stream_handle(stream) -> ctypes.c_void_p:
@@ -94,31 +120,37 @@ def _elementwise(name: str, a: torch.Tensor, b: torch.Tensor, out, stream) -> to
     return out
 
 
+@_on_stream
 def ff_add(a, b, out=None, stream=None):
     """Float-float sum a + b (Add22, section 4.1)."""
     return _elementwise("ff_add", a, b, out, stream)
 
 
+@_on_stream
 def ff_sub(a, b, out=None, stream=None):
     """Float-float difference a - b (Add22 of a and -b)."""
     return _elementwise("ff_sub", a, b, out, stream)
 
 
+@_on_stream
 def ff_mul(a, b, out=None, stream=None):
     """Float-float product a * b (Mul22, FMA TwoProd)."""
     return _elementwise("ff_mul", a, b, out, stream)
 
 
+@_on_stream
 def ff_mul_dekker(a, b, out=None, stream=None):
     """Float-float product a * b (Mul22 with Dekker's Split-based Mul12)."""
     return _elementwise("ff_mul_dekker", a, b, out, stream)
 
 
+@_on_stream
 def ff_div(a, b, out=None, stream=None):
     """Float-float quotient a / b (Div22, Dekker's div2)."""
     return _elementwise("ff_div", a, b, out, stream)
 
 
+@_on_stream
 def ff_add_accurate(a, b, out=None, stream=None):
     """Cancellation-safe float-float sum (AccurateDWPlusDW of Joldes, Muller
     and Popescu): relative error below 3u^2/(1 - 4u), u = 2^-24, also when
@@ -126,17 +158,20 @@ def ff_add_accurate(a, b, out=None, stream=None):
     return _elementwise("ff_add_accurate", a, b, out, stream)
 
 
+@_on_stream
 def ff_sub_accurate(a, b, out=None, stream=None):
     """Cancellation-safe float-float difference a - b."""
     return _elementwise("ff_sub_accurate", a, b, out, stream)
 
 
+@_on_stream
 def ff_mul_accurate(a, b, out=None, stream=None):
     """FMA-based float-float product (DWTimesDW3 of Joldes, Muller and
     Popescu): relative error at most 5u^2, u = 2^-24."""
     return _elementwise("ff_mul_accurate", a, b, out, stream)
 
 
+@_on_stream
 def ff_div_accurate(a, b, out=None, stream=None):
     """Reciprocal-based float-float quotient a / b (DWDivDW3 of Joldes,
     Muller and Popescu): relative error at most 9.8u^2, one division per
@@ -144,6 +179,7 @@ def ff_div_accurate(a, b, out=None, stream=None):
     return _elementwise("ff_div_accurate", a, b, out, stream)
 
 
+@_on_stream
 def ff_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> torch.Tensor:
     """dst <- src for float32 tensors (the bandwidth probe kernel)."""
     if src.dtype != torch.float32 or dst.dtype != torch.float32:
@@ -182,6 +218,7 @@ def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr())
 
 
+@_on_stream
 def ff_add12(a: torch.Tensor, b: torch.Tensor, out=None, stream=None) -> torch.Tensor:
     """Add12 theorem (section 4.1) elementwise on binary32 tensors: the
     float-float result (s, r) with s = a (+) b and s + r = a + b exactly."""
@@ -194,6 +231,7 @@ def ff_add12(a: torch.Tensor, b: torch.Tensor, out=None, stream=None) -> torch.T
     return out
 
 
+@_on_stream
 def ff_mul12(a: torch.Tensor, b: torch.Tensor, dekker: bool = False, out=None,
              stream=None) -> torch.Tensor:
     """Exact products elementwise: (x, y) with x = a (x) b, x + y = a b, by
@@ -218,16 +256,19 @@ def _f32_binary(name: str, a, b, out, stream) -> torch.Tensor:
     return out
 
 
+@_on_stream
 def f32_add(a, b, out=None, stream=None) -> torch.Tensor:
     """Binary32 a (+) b: the reference operator of the paper's tables."""
     return _f32_binary("ff_f32_add", a, b, out, stream)
 
 
+@_on_stream
 def f32_mul(a, b, out=None, stream=None) -> torch.Tensor:
     """Binary32 a (x) b: the reference operator of the paper's tables."""
     return _f32_binary("ff_f32_mul", a, b, out, stream)
 
 
+@_on_stream
 def f32_mad(a, b, c, out=None, stream=None) -> torch.Tensor:
     """Binary32 fma(a, b, c), one rounding: the tables' multiply-add."""
     _f32_operands("ff_f32_mad", a, b, c)
@@ -241,6 +282,7 @@ def f32_mad(a, b, c, out=None, stream=None) -> torch.Tensor:
 
 # ----------------------------------------------------------------- conversions
 
+@_on_stream
 def ff_from_f64(x: torch.Tensor, out=None, stream=None) -> torch.Tensor:
     """binary64 tensor -> float-float tensor (2, *x.shape): hi = fl32(x),
     lo = fl32(x - hi), on the device."""
@@ -258,6 +300,7 @@ def ff_from_f64(x: torch.Tensor, out=None, stream=None) -> torch.Tensor:
     return out
 
 
+@_on_stream
 def ff_to_f64(a: torch.Tensor, out=None, stream=None) -> torch.Tensor:
     """float-float tensor -> binary64 tensor: (double) hi + (double) lo, one
     rounding, on the device."""
@@ -307,11 +350,13 @@ def _horner_f32(name, coef, x, out, stream):
     return out
 
 
+@_on_stream
 def ff_horner_f32(coef, x, out=None, stream=None) -> torch.Tensor:
     """Horner's rule in binary32: sum_i coef[i] x^i at every point of x."""
     return _horner_f32("ff_horner_f32", coef, x, out, stream)
 
 
+@_on_stream
 def ff_horner_comp(coef, x, out=None, stream=None) -> torch.Tensor:
     """Compensated Horner (Graillat, Langlois and Louvet) at every point of
     x: binary32 results as accurate as Horner's rule in twice the working
@@ -319,6 +364,7 @@ def ff_horner_comp(coef, x, out=None, stream=None) -> torch.Tensor:
     return _horner_f32("ff_horner_comp", coef, x, out, stream)
 
 
+@_on_stream
 def ff_horner_ff(coef, x, out=None, stream=None, ff_points: bool = True) -> torch.Tensor:
     """Float-float Horner (Mul22 then Add22 per step).  coef: binary32
     (degree + 1,) or float-float (2, degree + 1); x: a float-float tensor
@@ -381,6 +427,7 @@ def _workspace(nbytes: int, device, workspace):
     return workspace
 
 
+@_on_stream
 def ff_dot_batched(x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, cfg=None,
                    out=None, workspace=None, stream=None) -> torch.Tensor:
     """Float-float dots of binary32 vectors: out[:, v] = sum of x*y over
@@ -405,6 +452,7 @@ def ff_dot_batched(x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, cfg=
     return out
 
 
+@_on_stream
 def ff_dot_batched_noalloc(x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, cfg=None,
                            out=None, stream=None) -> torch.Tensor:
     """ff_dot_batched through the entry point that takes no workspace (its
@@ -428,6 +476,7 @@ def ff_dot_batched_noalloc(x: torch.Tensor, y: torch.Tensor, offsets: torch.Tens
     return out
 
 
+@_on_stream
 def ff_dot2_batched(x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, cfg=None,
                     out=None, workspace=None, stream=None) -> torch.Tensor:
     """Compensated dots (Dot2 of Ogita, Rump and Oishi) of binary32 vectors:
@@ -451,6 +500,7 @@ def ff_dot2_batched(x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, cfg
     return out
 
 
+@_on_stream
 def ff_sum2_batched(x: torch.Tensor, offsets: torch.Tensor, cfg=None, out=None, workspace=None,
                     stream=None) -> torch.Tensor:
     """Compensated sums (Sum2 of Ogita, Rump and Oishi) of binary32
@@ -470,6 +520,7 @@ def ff_sum2_batched(x: torch.Tensor, offsets: torch.Tensor, cfg=None, out=None, 
     return out
 
 
+@_on_stream
 def ff_dot_ff_batched(x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, cfg=None,
                       out=None, workspace=None, stream=None) -> torch.Tensor:
     """Float-float dots of float-float vectors (Mul22 terms, Add22
@@ -494,6 +545,7 @@ def ff_dot_ff_batched(x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, c
     return out
 
 
+@_on_stream
 def ff_sum_batched(x: torch.Tensor, offsets: torch.Tensor, cfg=None, out=None, workspace=None,
                    stream=None) -> torch.Tensor:
     """Float-float sums of binary32 segments [offsets[v], offsets[v+1]) of x
@@ -513,6 +565,7 @@ def ff_sum_batched(x: torch.Tensor, offsets: torch.Tensor, cfg=None, out=None, w
     return out
 
 
+@_on_stream
 def ff_sum_ff_batched(x: torch.Tensor, offsets: torch.Tensor, cfg=None, out=None,
                       workspace=None, stream=None) -> torch.Tensor:
     """Float-float sums of float-float segments of x (shape (2, total))."""
@@ -555,6 +608,7 @@ def _check_matrix(A: torch.Tensor):
     return M, N, lda
 
 
+@_on_stream
 def ff_matvec(A: torch.Tensor, x: torch.Tensor, algo: int = MATVEC_FAST, out=None,
               stream=None) -> torch.Tensor:
     """y = A x for a float-float matrix A (2, M, N) and vector x (2, N)."""
@@ -573,6 +627,7 @@ def ff_matvec(A: torch.Tensor, x: torch.Tensor, algo: int = MATVEC_FAST, out=Non
     return out
 
 
+@_on_stream
 def ff_matvec_backward(A: torch.Tensor, x: torch.Tensor, g: torch.Tensor, want_dA: bool = True,
                        want_dx: bool = True, algo: int = MATVEC_FAST, stream=None):
     """Backward pass of y = A x for the upstream float-float gradient g (2, M):
@@ -598,6 +653,7 @@ def ff_matvec_backward(A: torch.Tensor, x: torch.Tensor, g: torch.Tensor, want_d
     return dA, dx
 
 
+@_on_stream
 def ff_dot_backward(g: torch.Tensor, x: torch.Tensor, y: torch.Tensor, want_dx: bool = True,
                     want_dy: bool = True, stream=None):
     """Backward pass of s = sum x_i y_i for an upstream float-float gradient
@@ -635,6 +691,7 @@ def _ff_or_f32_planes(t: torch.Tensor, name: str):
     return hi, lo, t.shape[1]
 
 
+@_on_stream
 def ff_dot_batched_backward(g: torch.Tensor, x: torch.Tensor, y: torch.Tensor,
                             offsets: torch.Tensor, want_dx: bool = True, want_dy: bool = True,
                             stream=None):
@@ -670,6 +727,7 @@ def ff_gemm_workspace_size(M: int, N: int, K: int, algo: int = GEMM_SLICED_I8) -
     return int(lib.ff_gemm_workspace_size(int(M), int(N), int(K), int(algo)))
 
 
+@_on_stream
 def ff_gemm(A: torch.Tensor, B: torch.Tensor, algo: int = GEMM_SLICED_I8, out=None,
             workspace=None, stream=None) -> torch.Tensor:
     """C = A B for float-float matrices A (2, M, K) and B (2, K, N)."""

@@ -8,6 +8,15 @@ respect to the represented number (which is also the derivative with respect
 to either plane).  The backward kernels read and write gradients in that
 form.  A scalar float-float loss is seeded with the float-float one,
 ``loss.backward(torch.tensor([1.0, 0.0], device=...))``.
+
+Ordinary torch operations on the planes follow the other convention: a loss
+computed from the value, e.g. ``(w * (y[0] + y[1])).sum()``, sends each
+plane its own partial derivative, and d/d(hi) = d/d(lo) = d/d(value), so
+both planes carry the same number g.  A normalised float-float gradient
+never has two equal planes except at zero (|lo| <= ulp(hi)/2), so the
+backward functions read an element whose two planes are equal as the value
+g itself, (g, g) -> (g, 0), and any other element as the float-float value
+hi + lo.  (Selecting a plane is exact; no arithmetic is involved.)
 """
 from __future__ import annotations
 
@@ -17,6 +26,15 @@ from . import (MATVEC_FAST, ff_dot_backward, ff_dot_batched_backward, ff_dot_ff_
                ff_matvec, ff_matvec_backward)
 
 __all__ = ["FFMatVec", "FFDot", "FFDotBatched", "ff_one"]
+
+
+def _value_gradient(g: torch.Tensor) -> torch.Tensor:
+    """The incoming gradient as a float-float value: elements whose two
+    planes are equal (the per-plane derivative delivered by ordinary torch
+    operations) keep plane 0 and get a zero low word."""
+    g = g.contiguous()
+    lo = torch.where(g[0] == g[1], torch.zeros_like(g[1]), g[1])
+    return torch.stack((g[0], lo))
 
 
 def ff_one(device="cuda") -> torch.Tensor:
@@ -37,7 +55,7 @@ class FFMatVec(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gy):
         A, x = ctx.saved_tensors
-        gy = gy.contiguous()
+        gy = _value_gradient(gy)
         dA, dx = ff_matvec_backward(A, x, gy, want_dA=ctx.needs_input_grad[0],
                                     want_dx=ctx.needs_input_grad[1], algo=ctx.algo)
         return dA, dx, None
@@ -57,7 +75,7 @@ class FFDot(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gs):
         u, v = ctx.saved_tensors
-        du, dv = ff_dot_backward(gs.contiguous(), u, v, want_dx=ctx.needs_input_grad[0],
+        du, dv = ff_dot_backward(_value_gradient(gs), u, v, want_dx=ctx.needs_input_grad[0],
                                  want_dy=ctx.needs_input_grad[1])
         return du, dv
 
@@ -75,7 +93,7 @@ class FFDotBatched(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gs):
         x, y, offsets = ctx.saved_tensors
-        dx, dy = ff_dot_batched_backward(gs.contiguous(), x, y, offsets,
+        dx, dy = ff_dot_batched_backward(_value_gradient(gs), x, y, offsets,
                                          want_dx=ctx.needs_input_grad[0],
                                          want_dy=ctx.needs_input_grad[1])
         return dx, dy, None

@@ -48,7 +48,7 @@ __device__ __forceinline__ void st_nt(T v, T *p) { __builtin_nontemporal_store(v
 
 // The kPer lane-contiguous elements b0 + kBlock * k of one plane; zero
 // past n.
-__device__ __forceinline__ void load_plane(const float *__restrict__ p, int64_t b0, int64_t n,
+__device__ __forceinline__ void load_plane(const float *p, int64_t b0, int64_t n,
                                            float (&v)[kPer])
 {
 #pragma unroll
@@ -58,13 +58,13 @@ __device__ __forceinline__ void load_plane(const float *__restrict__ p, int64_t 
     }
 }
 
+// No pointer is __restrict__: an output plane may be the same array as an
+// input plane (in place).  Each element is loaded before it is stored, by
+// the same thread, so in-place results equal out-of-place ones.
 template <class Tag>
-__global__ __launch_bounds__(kBlock) void ew_stream(const float *__restrict__ ah,
-                                                      const float *__restrict__ al,
-                                                      const float *__restrict__ bh,
-                                                      const float *__restrict__ bl,
-                                                      float *__restrict__ rh,
-                                                      float *__restrict__ rl, int64_t n)
+__global__ __launch_bounds__(kBlock) void ew_stream(const float *ah, const float *al,
+                                                      const float *bh, const float *bl,
+                                                      float *rh, float *rl, int64_t n)
 {
     const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kSpan + threadIdx.x;
     float xah[kPer], xal[kPer], xbh[kPer], xbl[kPer];
@@ -97,12 +97,9 @@ constexpr int64_t kSmallN = int64_t(1) << 22;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <class Tag>
-__global__ __launch_bounds__(kBlock) void ew_vec(const f32x4 *__restrict__ ah,
-                                                   const f32x4 *__restrict__ al,
-                                                   const f32x4 *__restrict__ bh,
-                                                   const f32x4 *__restrict__ bl,
-                                                   f32x4 *__restrict__ rh,
-                                                   f32x4 *__restrict__ rl, int64_t nvec)
+__global__ __launch_bounds__(kBlock) void ew_vec(const f32x4 *ah, const f32x4 *al,
+                                                   const f32x4 *bh, const f32x4 *bl, f32x4 *rh,
+                                                   f32x4 *rl, int64_t nvec)
 {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (i >= nvec)
@@ -129,8 +126,8 @@ __global__ __launch_bounds__(kBlock) void ew_vec(const f32x4 *__restrict__ ah,
 constexpr int kCopyThreads = 512;
 constexpr int kCopyPer = 4;
 
-__global__ __launch_bounds__(kCopyThreads) void copy_stream(const float *__restrict__ src,
-                                                           float *__restrict__ dst, int64_t n)
+__global__ __launch_bounds__(kCopyThreads) void copy_stream(const float *src, float *dst,
+                                                           int64_t n)
 {
     const int64_t b0 =
         static_cast<int64_t>(blockIdx.x) * (kCopyThreads * kCopyPer) + threadIdx.x;

@@ -164,6 +164,37 @@ def test_autograd_against_fp64_gradient_and_finite_differences():
         assert abs(fd - dx[i]) <= 1e-9 * max(1.0, abs(fd)), (i, fd, dx[i])
 
 
+def test_autograd_under_ordinary_torch_ops():
+    """Losses built from the dots' values with ordinary torch operations send
+    the same derivative to both planes; the backward functions read it as
+    that binary32 value, so the gradients are Mul22((c, 0), .), bit for bit."""
+    _announce("[gpu] FFDotBatched and FFDot under ordinary torch ops")
+    from paper_cs_0603115_amd.autograd import FFDot, FFDotBatched
+    lengths = [5, 0, 130, 1000, 3]
+    offs = _offsets(lengths, lead=2)
+    total = int(offs[-1]) + 4
+    x = fi.gaussian_ff((total,), 5041).cuda().requires_grad_(True)
+    y = fi.gaussian_ff((total,), 5042).cuda().requires_grad_(True)
+    w = fi.gaussian_f32((len(lengths),), 5043).cuda()
+    s = FFDotBatched.apply(x, y, torch.from_numpy(offs).cuda())
+    (w * (s[0] + s[1])).sum().backward()
+    g = torch.stack([w, torch.zeros_like(w)]).cpu().numpy()
+    want = oracle.dot_batched_backward(g[0], g[1], offs, *_planes(x.detach()),
+                                       *_planes(y.detach()))
+    _check(x.grad.cpu().numpy(), want[:2], "dx under torch ops")
+    _check(y.grad.cpu().numpy(), want[2:], "dy under torch ops")
+    # a single dot scaled by three after joining its planes
+    u = fi.gaussian_ff((777,), 5044).cuda().requires_grad_(True)
+    v = fi.gaussian_ff((777,), 5045).cuda().requires_grad_(True)
+    d = FFDot.apply(u, v)
+    (3.0 * (d[0] + d[1])).backward()
+    o = np.array([0, 777], np.int64)
+    want = oracle.dot_batched_backward(np.float32([3.0]), np.float32([0.0]), o,
+                                       *_planes(u.detach()), *_planes(v.detach()))
+    _check(u.grad.cpu().numpy(), want[:2], "FFDot du under torch ops")
+    _check(v.grad.cpu().numpy(), want[2:], "FFDot dv under torch ops")
+
+
 def _candidates_hold(d, g, y_h, y_l):
     """Every element of the gradient pair d is Mul22(g_v, y_i) for some v, or
     a zero pair: the property the entry point keeps for offsets that break

@@ -187,6 +187,43 @@ def test_autograd_matvec_then_dot():
     assert abs(frac(lv[0]) + frac(lv[1]) - exact) <= 2 * TWO_M44 * scale
 
 
+def test_autograd_matvec_under_ordinary_torch_ops():
+    """A loss built from y's value with ordinary torch operations sends the
+    same derivative to both planes; the backward reads it as that value
+    (not as the float-float sum of the two planes, which would double it)."""
+    _announce("[gpu] FFMatVec under ordinary torch ops")
+    from paper_cs_0603115_amd.autograd import FFMatVec
+    M, N = 160, 288
+    A = fi.gaussian_ff((M, N), 61).cuda().requires_grad_()
+    x = fi.gaussian_ff((N,), 62).cuda().requires_grad_()
+    w = fi.gaussian_f32((M,), 63).cuda()
+    y = FFMatVec.apply(A, x)
+    loss = (w * (y[0] + y[1])).sum()
+    loss.backward()
+    g = torch.stack([w, torch.zeros_like(w)])
+    check_dA_bits(x.detach(), g, A.grad, "dA under torch ops")
+    check_cols_exact(A.detach(), g, x.grad, "dx under torch ops")
+    # FP64 central differences of the same loss in a few coordinates of x
+    An = A.detach().cpu().double()
+    Av = An[0] + An[1]
+    xv = (x.detach().cpu().double())
+    xv = xv[0] + xv[1]
+    wv = w.cpu().double()
+    gx = x.grad.cpu().double()
+    for j in (0, 17, 101, N - 1):
+        e = torch.zeros(N, dtype=torch.float64)
+        e[j] = 1.0
+        fd = (wv @ (Av @ (xv + e)) - wv @ (Av @ (xv - e))) / 2
+        assert abs(float(gx[0, j] + gx[1, j]) - float(fd)) <= 2.0 ** -30 * float(
+            (wv.abs() @ Av.abs())[j]), j
+    # y.sum(): every value weighted by one
+    A.grad = x.grad = None
+    FFMatVec.apply(A, x).sum().backward()
+    ones = torch.stack([torch.ones(M), torch.zeros(M)]).cuda()
+    check_dA_bits(x.detach(), ones, A.grad, "dA of y.sum()")
+    check_cols_exact(A.detach(), ones, x.grad, "dx of y.sum()")
+
+
 def test_full_size_8192_matvec_and_backward():
     # Differentiable matvec at full size: A 8192 x 8192 float-float, x 8192,
     # w normal(0,1) binary32, loss = sum w * (A x).
