@@ -6,8 +6,8 @@
 // Each operator reads 16 bytes and writes 8 bytes per element and performs
 // at most ~45 VALU operations, far below the gfx950 ridge point (~236
 // binary32 operations per 24 bytes at 8 TB/s), so the kernels are
-// HBM-bound.  One workgroup of kBlock threads per block of kBlock * kPer
-// consecutive elements, in launch order; thread t takes elements
+// HBM-bound.  One workgroup of kBlock (128) threads per block of kBlock *
+// kPer (256) consecutive elements, in launch order; thread t takes elements
 // b0 + t + kBlock k (k < kPer) of every plane, so each wavefront access is
 // 256 contiguous bytes of a plane, issues all its non-temporal 4-byte loads
 // before any arithmetic, and stores non-temporally.  Any 4-byte alignment.
@@ -31,15 +31,19 @@ struct Mul22Accurate { static constexpr int op = ffd::OP_MUL_ACCURATE; };
 struct Div22Accurate { static constexpr int op = ffd::OP_DIV_ACCURATE; };
 
 // Launch shape chosen by sweeps on MI355X at N = 2^28 (Add22, Mul22,
-// Div22): kBlock 256-1024 threads by 1-32 elements per thread of 4-byte
-// lane-contiguous accesses, against one float4 group per plane per lane
-// (2-8 groups, persistent grids, XCD-contiguous orders and plane offsets
-// before that).  1024 threads by 2 elements moved 6.3-6.4 TB/s; the best
-// float4 form 5.8-5.95 TB/s.  Issuing the loads plane by plane added
-// another 1-1.5 % (6.31-6.36 TB/s).
-constexpr int kBlock = 1024;  // 16 wavefronts of 64 lanes
+// Div22), each over five fresh allocations of the planes: small workgroups
+// of kBlock = 128 threads by kPer = 2 lane-contiguous 4-byte elements moved
+// 6.5-6.6 TB/s (0.97-0.98 ms per operator) whatever the planes' relative
+// placement, against 6.2-6.35 TB/s for the earlier 1024 by 2 (which needed
+// the planes' starts skewed by a few KiB to approach 6.4) and 6.1-6.4 TB/s
+// for 256 or 512 by 2; 64 threads, 1 or 3 elements per thread, and 8-byte
+// (float2) accesses per lane were all slower.  Issuing the loads plane by
+// plane measured 1-1.5 % faster than element by element.
+constexpr int kBlock = 128;   // 2 wavefronts of 64 lanes
 constexpr int kPer = 2;       // elements per thread per plane
 constexpr int64_t kSpan = static_cast<int64_t>(kBlock) * kPer;
+// The float4 path for cache-resident sizes keeps 1024-thread workgroups.
+constexpr int kVecBlock = 1024;
 
 template <typename T>
 __device__ __forceinline__ T ld_nt(const T *p) { return __builtin_nontemporal_load(p); }
@@ -97,11 +101,11 @@ constexpr int64_t kSmallN = int64_t(1) << 22;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <class Tag>
-__global__ __launch_bounds__(kBlock) void ew_vec(const f32x4 *ah, const f32x4 *al,
+__global__ __launch_bounds__(kVecBlock) void ew_vec(const f32x4 *ah, const f32x4 *al,
                                                    const f32x4 *bh, const f32x4 *bl, f32x4 *rh,
                                                    f32x4 *rl, int64_t nvec)
 {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kVecBlock + threadIdx.x;
     if (i >= nvec)
         return;
     const f32x4 xah = ld_nt(ah + i), xal = ld_nt(al + i), xbh = ld_nt(bh + i),
@@ -168,8 +172,8 @@ ff_status elementwise(const float *ah, const float *al, const float *bh, const f
         const int64_t nvec = n / 4;
         done = 4 * nvec;
         if (nvec > 0)
-            hipLaunchKernelGGL(ew_vec<Tag>, dim3(static_cast<unsigned>(ffh::cdiv(nvec, kBlock))),
-                               dim3(kBlock), 0, stream, reinterpret_cast<const f32x4 *>(ah),
+            hipLaunchKernelGGL(ew_vec<Tag>, dim3(static_cast<unsigned>(ffh::cdiv(nvec, kVecBlock))),
+                               dim3(kVecBlock), 0, stream, reinterpret_cast<const f32x4 *>(ah),
                                reinterpret_cast<const f32x4 *>(al),
                                reinterpret_cast<const f32x4 *>(bh),
                                reinterpret_cast<const f32x4 *>(bl), reinterpret_cast<f32x4 *>(rh),

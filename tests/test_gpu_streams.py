@@ -9,7 +9,10 @@ side stream first (so the side stream's kernels start late), then the
 reduction or product under test, then allocates and overwrites memory of
 the same size on the current stream before any synchronisation, and finally
 compares the side stream's result bit for bit with the same call made on the
-current stream alone.
+current stream alone.  Whether the two streams really run concurrently
+depends on how the runtime maps them to hardware queues, so each case also
+checks the cause directly: the allocator segment holding the output belongs
+to the side stream.
 """
 import sys
 
@@ -38,6 +41,15 @@ def _busy(ff, stream, n=1 << 26, reps=4):
     return a, b, out
 
 
+def _owner_stream(t):
+    """The stream of torch's allocator segment holding tensor t."""
+    ptr = t.data_ptr()
+    for seg in torch.cuda.memory_snapshot():
+        if seg["address"] <= ptr < seg["address"] + seg["total_size"]:
+            return seg["stream"]
+    raise AssertionError("tensor not found in the allocator snapshot")
+
+
 def _scribble(nbytes, times=4):
     """Allocate and overwrite blocks of nbytes on the current stream."""
     keep = []
@@ -57,6 +69,7 @@ def test_batched_dot_on_a_side_stream():
     side = torch.cuda.Stream()
     keep = _busy(ff, side)
     got = ff.ff_dot_batched(x, y, offs, stream=side)
+    assert _owner_stream(got) == side.cuda_stream
     nbytes = ff.ff_dot_batched_workspace_size(x.numel(), 600)
     junk = _scribble(nbytes) + _scribble(got.numel() * 4)
     torch.cuda.synchronize()
@@ -74,6 +87,7 @@ def test_sliced_gemm_on_a_side_stream():
     side = torch.cuda.Stream()
     keep = _busy(ff, side)
     got = ff.ff_gemm(A, B, stream=side)
+    assert _owner_stream(got) == side.cuda_stream
     junk = _scribble(ff.ff_gemm_workspace_size(384, 256, 512)) + _scribble(got.numel() * 4)
     torch.cuda.synchronize()
     assert np.array_equal(got.cpu().numpy().view(np.uint32), want.cpu().numpy().view(np.uint32))
@@ -92,6 +106,7 @@ def test_matvec_backward_on_a_side_stream_by_handle():
     side = torch.cuda.Stream()
     keep = _busy(ff, side)
     dA, dx = ff.ff_matvec_backward(A, x, g, stream=side.cuda_stream)
+    assert _owner_stream(dx) == side.cuda_stream
     nbytes = int(ff.lib.ff_matvec_backward_workspace_size(1024, 768, 0))
     junk = _scribble(nbytes) + _scribble(dx.numel() * 4) + _scribble(dA.numel() * 4, times=1)
     torch.cuda.synchronize()
