@@ -11,15 +11,16 @@
 // (each wavefront load or store is one contiguous segment of a plane), all
 // loads of a thread issued before the arithmetic, non-temporal loads and
 // stores; any 4-byte (binary32) and 8-byte (binary64) alignment.  Shapes from
-// a sweep on MI355X at N = 2^28: from binary64, 256 threads by 4 elements
-// (6.25 TB/s, against 5.9 for one float4 group per plane and lane); to
-// binary64, 1024 threads by one element (6.0 TB/s, against 5.2).
+// sweeps on MI355X at N = 2^28: from binary64, 128 threads by 2 elements
+// (6.6 TB/s, against 6.3 for 256 by 4 and 5.9 for one float4 group per plane
+// and lane); to binary64, 1024 threads by one element (6.0 TB/s; 128- and
+// 256-thread workgroups by 2 or 4 elements reached 4.8-5.1).
 #include "ff_device.h"
 #include "ff_host.h"
 
 namespace ffk {
 
-constexpr int kFromThreads = 256, kFromPer = 4;
+constexpr int kFromThreads = 128, kFromPer = 2;
 constexpr int kToThreads = 1024, kToPer = 1;
 
 __device__ __forceinline__ void split_f64(double x, float &hi, float &lo)

@@ -6,8 +6,8 @@
 //   binary32 add, multiply and multiply-add (one rounding).
 //
 // Same streaming structure as the float-float operators: workgroups in
-// launch order, lane-contiguous elements (1024 threads by 2 per plane for the
-// kernels with two output planes, 256 by 4 for those with one), all 4-byte
+// launch order, lane-contiguous elements (128 threads by 2 per plane, or 256
+// by 4 for binary32 Add and Mul), all 4-byte
 // non-temporal loads issued before the arithmetic (plane by plane where the
 // kernel writes two planes), any 4-byte alignment; one float4 group per plane
 // and thread below 2^22 elements.  Bytes per element: 12 (add, mul), 16 (mad,
@@ -98,15 +98,17 @@ __global__ __launch_bounds__(kStreamBlock) void stream_vec(StreamPlanes<Op::kIn,
         __builtin_nontemporal_store(y[k], reinterpret_cast<f32x4 *>(p.out[k]) + g);
 }
 
-// Launch shape of the lane-contiguous form, by the number of output planes
-// (measured at N = 2^28): two outputs (Add12, Mul12) stream fastest with
-// 1024 threads by 2 elements, the elementwise operators' shape; one output
-// (binary32 Add, Mul, Mad) with 256 threads by 4 elements, 5-13 % faster
-// there (Add: 0.49 against 0.56 ms, 6.5 TB/s).
+// Launch shape of the lane-contiguous form, from sweeps at N = 2^28: the
+// float-float operators' 128 threads by 2 elements for Add12 and Mul12 (two
+// output planes; 6.4 TB/s, against 6.2 for 1024 by 2) and for the
+// three-input Mad (6.6 TB/s, against 6.3 for 256 by 4); 256 by 4 for the
+// two-input, one-output binary32 Add and Mul (6.4 TB/s; 128 by 4 ties, 128
+// by 2 is 2 % slower).
 template <class Op>
 struct StreamShape {
-    static constexpr int kBlock = Op::kOut >= 2 ? 1024 : 256;
-    static constexpr int kPer = Op::kOut >= 2 ? 2 : 4;   // elements per thread per plane
+    static constexpr bool kWide = Op::kOut == 1 && Op::kIn == 2;
+    static constexpr int kBlock = kWide ? 256 : 128;
+    static constexpr int kPer = kWide ? 4 : 2;   // elements per thread per plane
     static constexpr int64_t kSpan = static_cast<int64_t>(kBlock) * kPer;
 };
 
