@@ -89,8 +89,9 @@ def parse_args(argv=None):
                    help="target duration of the CPU-baseline sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--dot-cfg", default=None,
-                   help="block,chunk,grid,unroll of the batched dot; skips the autotuner "
-                        "(so that a profile holds only launches of this shape)")
+                   help="block,chunk,grid,unroll of the batched dot (for example 256,4096,0,16); "
+                        "skips the autotuner (so that a profile holds only launches of this "
+                        "shape)")
     p.add_argument("--no-secondary", action="store_true",
                    help="skip the batched-dot, Horner, GEMM, matvec and conversion measurements")
     return p.parse_args(argv)
@@ -264,7 +265,9 @@ def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
     total = x.numel()
     cfg = tuple(dot_cfg) if dot_cfg is not None else autotune.dot_cfg(x, y, offs)
     res = ff.ff_empty((offs.numel() - 1,), device=dev)
-    ws = torch.empty(ff.ff_dot_batched_workspace_size(total, offs.numel() - 1, cfg),
+    # large enough for the tuned shape and for every entry point's default
+    ws = torch.empty(max(ff.ff_dot_batched_workspace_size(total, offs.numel() - 1, cfg),
+                         ff.ff_dot_batched_workspace_size(total, offs.numel() - 1)),
                      dtype=torch.uint8, device=dev)
     ms = _time_launches(lambda: ff.ff_dot_batched(x, y, offs, cfg=cfg, out=res, workspace=ws,
                                                   stream=stream), 10, stream)
@@ -288,18 +291,18 @@ def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
     msb = _time_launches(dot_bwd, 10, stream)
     gbsb = 24 * total / (msb * 1e-3) / 1e9
     del dxb, dyb, gvec
-    # the other entry points of the family on the same batch and launch shape:
-    # float-float inputs (16 B per element), sums of binary32 (4 B) and of
-    # float-float (8 B) terms
+    # the other entry points of the family on the same batch, each with its
+    # default launch shape: float-float inputs (16 B per element), sums of
+    # binary32 (4 B) and of float-float (8 B) terms
     xf = torch.stack([x, torch.zeros_like(x)])
     yf = torch.stack([y, torch.zeros_like(y)])
     family = {}
     for name, fn, bpe in (
-            ("dot_ff_inputs", lambda: ff.ff_dot_ff_batched(xf, yf, offs, cfg=cfg, out=res,
+            ("dot_ff_inputs", lambda: ff.ff_dot_ff_batched(xf, yf, offs, out=res,
                                                            workspace=ws, stream=stream), 16),
-            ("sum_f32", lambda: ff.ff_sum_batched(x, offs, cfg=cfg, out=res, workspace=ws,
+            ("sum_f32", lambda: ff.ff_sum_batched(x, offs, out=res, workspace=ws,
                                                   stream=stream), 4),
-            ("sum_ff", lambda: ff.ff_sum_ff_batched(xf, offs, cfg=cfg, out=res, workspace=ws,
+            ("sum_ff", lambda: ff.ff_sum_ff_batched(xf, offs, out=res, workspace=ws,
                                                     stream=stream), 8)):
         msf = _time_launches(fn, 10, stream)
         gbf = bpe * total / (msf * 1e-3) / 1e9

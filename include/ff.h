@@ -192,37 +192,44 @@ ff_status ff_div_accurate(const float *a_hi, const float *a_lo,
  * work (section 7).
  *
  * Execution: four launches on `stream`: a planning launch (chunk counts and
- * their scan), one writing each chunk's element range, ONE persistent
- * launch that walks all chunks of all vectors, and one combining each
- * vector's partials.  Each chunk of `cfg->chunk` elements is reduced by one
- * wavefront (per-lane float-float accumulators, then a butterfly of Add22
- * over lane shuffles) into a float-float partial; one wavefront per vector
- * then adds the vector's partials with an Add22 tree of fixed shape.  No atomics are
- * used: for a given cfg the result is bitwise reproducible run to run.
- * Different cfg values may give different (equally valid) last bits.
+ * their scan), one writing each chunk's element range, one reducing the
+ * chunks -- one workgroup per chunk of block * unroll elements, launched in
+ * chunk order so that the resident workgroups stream memory together; each
+ * thread adds its `unroll` terms in order into a float-float accumulator,
+ * then a butterfly of Add22 over lane shuffles and the wavefronts' sums in
+ * index order give the chunk's float-float partial -- and one combining
+ * each vector's partials (one wavefront per vector, an Add22 tree of fixed
+ * shape).  No atomics are used: for a given cfg the result is bitwise
+ * reproducible run to run.  Different cfg values may give different
+ * (equally valid) last bits.  Any 4-byte alignment of the inputs.
  *
  * Accuracy: |result - exact| is bounded by (tree depth) * 2^-44 * sum|x_i y_i|
  * in the worst case; on random data it is far smaller (2^-47.1 sum|x_i y_i|
  * at worst over a batch of 4096 vectors of 64 to 2^20 normal(0,1) terms).
  */
 
-/* Launch shape of the batched dot.  All-zero fields select the defaults. */
+/* Launch shape of the batched reductions.  Zero fields select the entry
+ * point's default: 256 threads by 16 elements per thread for binary32
+ * inputs (dots, sums, Dot2, Sum2), 256 by 8 for float-float inputs. */
 typedef struct ff_dot_cfg {
-    int32_t block;  /* threads per workgroup: 256 or 512 (0: 512)           */
-    int32_t chunk;  /* elements per chunk, a multiple of 4, >= 64 (0: 16384) */
-    int32_t grid;   /* persistent workgroups; 0: 8 per compute unit          */
-    int32_t unroll; /* float4 groups per lane per step: 1, 2, 4, 8 (0: 8)   */
+    int32_t block;  /* threads per workgroup: 64, 128, 256 or 512            */
+    int32_t chunk;  /* elements per chunk: 0 or block * unroll (with unroll
+                       0, a chunk given sets unroll = chunk / block)         */
+    int32_t grid;   /* reserved: must be 0 (one workgroup per chunk)         */
+    int32_t unroll; /* elements per thread and input plane: 1, 2, 4, 8, 16
+                       or 32                                                 */
 } ff_dot_cfg;
 
-/* Bytes of device workspace ff_dot_batched / ff_dot_ff_batched need for
- * nvec vectors holding total_len elements in all (cfg NULL: defaults).
- * Returns 0 for invalid arguments. */
+/* Bytes of device workspace the batched reductions need for nvec vectors
+ * holding total_len elements in all, with this cfg (zero fields resolved
+ * with the smallest default chunk, 2048, so that the size serves every
+ * entry point).  Returns 0 for invalid arguments. */
 size_t ff_dot_batched_workspace_size(int64_t total_len, int32_t nvec,
                                      const ff_dot_cfg *cfg);
 
 /* out[v] = sum over [offsets[v], offsets[v+1]) of x_i * y_i, binary32
  * inputs, float-float result (out_hi[v], out_lo[v]).
- *   x, y       device, total_len binary32 each (16-byte aligned: fast path)
+ *   x, y       device, total_len binary32 each
  *   offsets    device, nvec + 1 int64, non-decreasing, offsets[0] >= 0,
  *              offsets[nvec] <= total_len (violations give unspecified
  *              results but never access memory outside the arrays)
@@ -286,7 +293,7 @@ ff_status ff_sum2_batched(const float *x, const int64_t *offsets, int32_t nvec,
                           void *stream);
 
 /* Capacity of the static scratch array of ff_dot_batched_noalloc (bytes). */
-#define FF_NOALLOC_SCRATCH_BYTES ((size_t)4 << 20)
+#define FF_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
 
 /* ff_dot_batched without a workspace argument, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
@@ -295,11 +302,12 @@ ff_status ff_sum2_batched(const float *x, const int64_t *offsets, int32_t nvec,
  * static device array of FF_NOALLOC_SCRATCH_BYTES inside the library, one
  * copy per device, held until the process ends (its device address is looked
  * up once per device on the first call there).  No allocation of any kind.
- * Limit: the batch must satisfy ff_dot_batched_workspace_size(total_len,
- * nvec, cfg) <= FF_NOALLOC_SCRATCH_BYTES, otherwise FF_ERR_WORKSPACE (with
- * the default cfg, for example, 4096 vectors of up to 2.77e9 elements in
- * all).  Nothing in the scratch needs to start at zero: every word a launch
- * reads was written earlier in the same call.  Every call on one device
+ * Limit: the batch's workspace (ff_dot_batched_workspace_size(total_len,
+ * nvec, cfg), here resolved with ff_dot_batched's own defaults) must not
+ * exceed FF_NOALLOC_SCRATCH_BYTES, otherwise FF_ERR_WORKSPACE (with the
+ * default cfg, for example, 4096 vectors of up to 2.8e9 elements in all).
+ * Nothing in the scratch needs to start at zero: every word a launch reads
+ * was written earlier in the same call.  Every call on one device
  * shares that device's array, so calls that may overlap on one device (two
  * streams, two host threads) race and give unspecified results; calls on
  * one stream are ordered and safe.  Errors: those of ff_dot_batched, and
@@ -310,13 +318,13 @@ ff_status ff_dot_batched_noalloc(const float *x, const float *y,
                                  float *out_hi, float *out_lo, void *stream);
 
 /* Launch-shape autotuner for ff_dot_batched on this batch: times every
- * candidate (block 256/512 x unroll 1/2/4/8 x chunk 1024..32768 x 2..16
- * workgroups per compute unit) whose workspace fits in ws_bytes, `reps`
- * launches each after one untimed launch, with HIP events on `stream`, and
- * returns the fastest in *best with its mean time in *best_ms.  SYNCHRONOUS:
- * waits for each candidate.  out_hi/out_lo receive the last candidate's
- * result.  Errors: those of ff_dot_batched, FF_ERR_NULL (best/best_ms),
- * FF_ERR_ARG (reps < 1), FF_ERR_WORKSPACE (no candidate fits). */
+ * candidate (block 64/128/256/512 x unroll 4/8/16/32) whose workspace fits
+ * in ws_bytes, `reps` launches each after one untimed launch, with HIP
+ * events on `stream`, and returns the fastest in *best with its mean time in
+ * *best_ms.  SYNCHRONOUS: waits for each candidate.  out_hi/out_lo receive
+ * the last candidate's result.  Errors: those of ff_dot_batched, FF_ERR_NULL
+ * (best/best_ms), FF_ERR_ARG (reps < 1), FF_ERR_WORKSPACE (no candidate
+ * fits). */
 ff_status ff_dot_batched_autotune(const float *x, const float *y,
                                   const int64_t *offsets, int32_t nvec,
                                   int64_t total_len, void *ws, size_t ws_bytes,

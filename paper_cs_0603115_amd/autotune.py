@@ -35,10 +35,16 @@ def device_key(device) -> str:
     return f"{arch}-cu{props.multi_processor_count}"
 
 
+# Version of the launch-shape format (block, chunk, grid, unroll) the entries
+# hold: entries of another version are not reused.
+SHAPE_FORMAT = 2
+
+
 def shape_class(total_len: int, nvec: int) -> str:
     """Batches whose total length and vector count agree to a factor of two
     share one entry."""
-    return f"dot-t{int(math.log2(total_len + 1))}-v{int(math.log2(nvec + 1))}"
+    return (f"dot{SHAPE_FORMAT}-t{int(math.log2(total_len + 1))}"
+            f"-v{int(math.log2(nvec + 1))}")
 
 
 def _load() -> dict:
@@ -70,7 +76,7 @@ def tune_dot(x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor, reps: int 
     Returns ((block, chunk, grid, unroll), mean milliseconds)."""
     nvec = offsets.numel() - 1
     total = x.numel()
-    smallest = DotCfg(256, 4096, 0, 1)
+    smallest = DotCfg(64, 256, 0, 4)   # the search's smallest chunk
     nbytes = int(lib.ff_dot_batched_workspace_size(total, nvec, ctypes.byref(smallest)))
     ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=x.device)
     out = torch.empty((2, nvec), dtype=torch.float32, device=x.device)

@@ -2,16 +2,24 @@
 //
 // Data: vector v is [offsets[v], offsets[v+1]) of the concatenated inputs
 // (binary32 x, y, or float-float planes xh, xl, yh, yl).  A vector is cut
-// into chunks of `chunk` elements.  Four stream-ordered launches:
+// into chunks of `chunk` = block * unroll elements.  Four stream-ordered
+// launches:
 //   plan      one workgroup: chunk counts per vector and their exclusive scan
 //   records   one wavefront per vector: the element range of each chunk
-//   partials  persistent: each wavefront of the grid is a worker, and chunk
-//             c is reduced by worker c mod (grid * waves per workgroup) into
-//             a float-float partial
+//   partials  one workgroup per chunk, launched in chunk order (which is
+//             memory order): thread t takes the chunk's elements t + block k
+//             (k < unroll) of every plane with 4-byte loads, all issued
+//             before any arithmetic, accumulates them in order, and the
+//             workgroup reduces its threads to the chunk's float-float partial
 //   combine   one wavefront per vector: Add22 of the vector's partials
-// Launch boundaries order the phases, so no fences or atomics are needed: a
-// device-scope fence on gfx950 writes back and invalidates the L2 of the
-// issuing XCD, which per chunk cost more than the chunk's own traffic.
+// The resident workgroups of the partials launch sweep memory together, the
+// pattern the HBM streams fastest (the elementwise operators' lesson): on
+// the 4096-vector batch it moved 0.80 of the HBM peak for all four input
+// kinds and any placement of the planes, where persistent workers reducing
+// chunks spread over memory had reached 0.80 for binary32 dots but 0.60-0.75
+// for float-float inputs and sums.  Launch boundaries order the phases, so no
+// fences or atomics are needed: a device-scope fence on gfx950 writes back and
+// invalidates the L2 of the issuing XCD.
 //
 // Per element the binary32 path reads 8 bytes and performs TwoProd (2 VALU)
 // plus Add22 (~14 VALU): ~2 operations per byte, under the ~9.8 ops/byte
@@ -30,8 +38,6 @@
 #include "ff_host.h"
 
 namespace ffk {
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPlanBlock = 1024;
 
@@ -242,31 +248,30 @@ __global__ __launch_bounds__(256) void dot_combine(int32_t nvec, Workspace w,
     }
 }
 
-// Input kinds.  Terms<In> loads the float4 group g (elements 4g .. 4g+3)
-// of every input plane, and forms each element's exact term as a pair
-// (TwoProd of binary32 inputs, Mul22 of float-float inputs, the value
-// itself for sums).
+// Input kinds.  Terms<In>::load reads element i of every input plane (one
+// 4-byte load each) and Terms<In>::term forms the element's exact term as a
+// pair: TwoProd of binary32 inputs, Mul22 of float-float inputs, the value
+// itself for sums.
 struct InF32 {
     const float *x, *y;
+    static constexpr int kPlanes = 2;
 };
 struct InFF {
     const float *xh, *xl, *yh, *yl;
+    static constexpr int kPlanes = 4;
 };
 struct InSumF32 {
     const float *x;
+    static constexpr int kPlanes = 1;
 };
 struct InSumFF {
     const float *xh, *xl;
+    static constexpr int kPlanes = 2;
 };
 
-template <int P>
-struct Planes {
-    f32x4 p[P];
-};
-
-__device__ __forceinline__ f32x4 load_group(const float *a, int64_t g)
+__device__ __forceinline__ float load_nt(const float *p, int64_t i)
 {
-    return __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(a) + g);
+    return __builtin_nontemporal_load(p + i);
 }
 
 template <class In>
@@ -274,229 +279,184 @@ struct Terms;
 
 template <>
 struct Terms<InF32> {
-    using G = Planes<2>;
-    __device__ __forceinline__ static G load(const InF32 &in, int64_t g)
+    __device__ __forceinline__ static void load(const InF32 &in, int64_t i, float *v)
     {
-        return G{{load_group(in.x, g), load_group(in.y, g)}};
+        v[0] = load_nt(in.x, i);
+        v[1] = load_nt(in.y, i);
     }
-    __device__ __forceinline__ static void term(const G &q, int k, float &ph, float &pl)
+    __device__ __forceinline__ static void term(const float *v, float &ph, float &pl)
     {
-        ffd::mul12_fma(q.p[0][k], q.p[1][k], ph, pl);
-    }
-    __device__ __forceinline__ static void one(const InF32 &in, int64_t i, float &ph, float &pl)
-    {
-        ffd::mul12_fma(in.x[i], in.y[i], ph, pl);
+        ffd::mul12_fma(v[0], v[1], ph, pl);
     }
 };
 
 template <>
 struct Terms<InFF> {
-    using G = Planes<4>;
-    __device__ __forceinline__ static G load(const InFF &in, int64_t g)
+    __device__ __forceinline__ static void load(const InFF &in, int64_t i, float *v)
     {
-        return G{{load_group(in.xh, g), load_group(in.xl, g), load_group(in.yh, g),
-                  load_group(in.yl, g)}};
+        v[0] = load_nt(in.xh, i);
+        v[1] = load_nt(in.xl, i);
+        v[2] = load_nt(in.yh, i);
+        v[3] = load_nt(in.yl, i);
     }
-    __device__ __forceinline__ static void term(const G &q, int k, float &ph, float &pl)
+    __device__ __forceinline__ static void term(const float *v, float &ph, float &pl)
     {
-        ffd::mul22<false>(q.p[0][k], q.p[1][k], q.p[2][k], q.p[3][k], ph, pl);
-    }
-    __device__ __forceinline__ static void one(const InFF &in, int64_t i, float &ph, float &pl)
-    {
-        ffd::mul22<false>(in.xh[i], in.xl[i], in.yh[i], in.yl[i], ph, pl);
+        ffd::mul22<false>(v[0], v[1], v[2], v[3], ph, pl);
     }
 };
 
 template <>
 struct Terms<InSumF32> {
-    using G = Planes<1>;
-    __device__ __forceinline__ static G load(const InSumF32 &in, int64_t g)
+    __device__ __forceinline__ static void load(const InSumF32 &in, int64_t i, float *v)
     {
-        return G{{load_group(in.x, g)}};
+        v[0] = load_nt(in.x, i);
     }
     // term = (x_i, 0): the binary32 value itself
-    __device__ __forceinline__ static void term(const G &q, int k, float &ph, float &pl)
+    __device__ __forceinline__ static void term(const float *v, float &ph, float &pl)
     {
-        ph = q.p[0][k];
-        pl = 0.0f;
-    }
-    __device__ __forceinline__ static void one(const InSumF32 &in, int64_t i, float &ph,
-                                               float &pl)
-    {
-        ph = in.x[i];
+        ph = v[0];
         pl = 0.0f;
     }
 };
 
 template <>
 struct Terms<InSumFF> {
-    using G = Planes<2>;
-    __device__ __forceinline__ static G load(const InSumFF &in, int64_t g)
+    __device__ __forceinline__ static void load(const InSumFF &in, int64_t i, float *v)
     {
-        return G{{load_group(in.xh, g), load_group(in.xl, g)}};
+        v[0] = load_nt(in.xh, i);
+        v[1] = load_nt(in.xl, i);
     }
-    __device__ __forceinline__ static void term(const G &q, int k, float &ph, float &pl)
+    __device__ __forceinline__ static void term(const float *v, float &ph, float &pl)
     {
-        ph = q.p[0][k];
-        pl = q.p[1][k];
-    }
-    __device__ __forceinline__ static void one(const InSumFF &in, int64_t i, float &ph,
-                                               float &pl)
-    {
-        ph = in.xh[i];
-        pl = in.xl[i];
+        ph = v[0];
+        pl = v[1];
     }
 };
 
-template <class In, class Acc>
-__device__ __forceinline__ void add_group(const typename Terms<In>::G &q, float2 acc[4])
-{
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        float ph, pl;
-        Terms<In>::term(q, k, ph, pl);
-        Acc::add(acc[k].x, acc[k].y, ph, pl);
-    }
-}
-
-// The persistent partials launch.  Each wavefront is an independent worker:
-// global wavefront w reduces chunks w, w + W, w + 2W, ... (W wavefronts in
-// the grid) to a partial with a butterfly, no barriers.
-// VEC (all planes 16-byte aligned): the float4 groups lying wholly inside
-// the chunk are read UNROLL at a time per lane, all loads issued before any
-// arithmetic; the at most 3 + 3 elements before the first and after the
-// last whole group are read one by one.  Otherwise every element is read
-// on its own.
-template <class In, class Acc, int BLOCK, int UNROLL, bool VEC>
-__global__ __launch_bounds__(BLOCK) void dot_partials(In in, Workspace w, int32_t nvec)
+// The partials launch: workgroup c reduces chunk c (c < the chunk count;
+// the grid holds the capacity, and the workgroups past the count return).
+// Thread t loads the chunk's elements s + t + BLOCK k, k < PER, of every
+// plane (each wavefront load is 256 contiguous bytes of a plane; any 4-byte
+// alignment), then adds their terms in k order into one float-float
+// accumulator.  A butterfly over the wavefront, then the wavefronts' sums in
+// index order, give the chunk's partial.  The order is fixed by (BLOCK,
+// PER), so results are reproducible run to run.
+template <class In, class Acc, int BLOCK, int PER>
+__global__ __launch_bounds__(BLOCK) void dot_chunks(In in, Workspace w, int32_t nvec)
 {
     constexpr int kWaves = BLOCK / 64;
-    const int lane = threadIdx.x & 63;
-    const int64_t gw = static_cast<int64_t>(blockIdx.x) * kWaves + (threadIdx.x >> 6);
-    const int64_t nw = static_cast<int64_t>(gridDim.x) * kWaves;
+    __shared__ float2 wave_part[kWaves];
+    const int64_t c = blockIdx.x;
     int64_t nchunks = w.chunk_start[nvec];
     if (nchunks > w.cap)
         nchunks = w.cap;
-
-    for (int64_t c = gw; c < nchunks; c += nw) {
-        const longlong2 r = w.ranges[c];
-        const int64_t s = r.x, e = r.y;
-
-        float2 acc[4];
+    if (c >= nchunks)
+        return;
+    const longlong2 r = w.ranges[c];
+    const int64_t s = r.x, e = r.y;   // s < e: recorded chunks are not empty
+    const int t = threadIdx.x;
+    float v[PER][In::kPlanes];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            acc[k] = make_float2(0.0f, 0.0f);
-        if (VEC) {
-            const int64_t ga = (s + 3) >> 2;   // first whole group
-            int64_t gb = e >> 2;               // end of the whole groups
-            if (gb < ga)
-                gb = ga;                       // s and e inside one group
-            int64_t g = ga + lane;
-            for (; g + (UNROLL - 1) * 64 < gb; g += 64 * UNROLL) {
-                typename Terms<In>::G q[UNROLL];
+    for (int k = 0; k < PER; ++k) {
+        const int64_t i = s + t + static_cast<int64_t>(BLOCK) * k;
+        Terms<In>::load(in, i < e ? i : s, v[k]);   // past the end: a harmless in-range load
+    }
+    float h = 0.0f, l = 0.0f;
 #pragma unroll
-                for (int u = 0; u < UNROLL; ++u)
-                    q[u] = Terms<In>::load(in, g + u * 64);
-#pragma unroll
-                for (int u = 0; u < UNROLL; ++u)
-                    add_group<In, Acc>(q[u], acc);
-            }
-            for (; g < gb; g += 64)
-                add_group<In, Acc>(Terms<In>::load(in, g), acc);
-            // head [s, 4 ga) and tail [4 gb, e) elements, by lanes 0..2 and
-            // 32..34 (when a chunk lies inside one group, gb = ga and the
-            // head covers it)
-            const int64_t head_end = 4 * ga < e ? 4 * ga : e;
-            const int64_t tail_beg = 4 * gb > s ? 4 * gb : s;
-            int64_t i = -1;
-            if (lane < 3 && s + lane < head_end)
-                i = s + lane;
-            else if (lane >= 32 && lane < 35 && tail_beg + (lane - 32) < e)
-                i = tail_beg + (lane - 32);
-            if (i >= 0) {
-                float ph, pl;
-                Terms<In>::one(in, i, ph, pl);
-                Acc::add(acc[0].x, acc[0].y, ph, pl);
-            }
-        } else {
-            for (int64_t i = s + lane; i < e; i += 64) {
-                float ph, pl;
-                Terms<In>::one(in, i, ph, pl);
-                Acc::add(acc[0].x, acc[0].y, ph, pl);
-            }
+    for (int k = 0; k < PER; ++k) {
+        const int64_t i = s + t + static_cast<int64_t>(BLOCK) * k;
+        if (i < e) {
+            float ph, pl;
+            Terms<In>::term(v[k], ph, pl);
+            Acc::add(h, l, ph, pl);
         }
-        float h = acc[0].x, l = acc[0].y;
-        Acc::merge(h, l, acc[1].x, acc[1].y);
-        float h2 = acc[2].x, l2 = acc[2].y;
-        Acc::merge(h2, l2, acc[3].x, acc[3].y);
-        Acc::merge(h, l, h2, l2);
-        wave_allreduce<Acc>(h, l);
-        if (lane == 0)
-            w.partials[c] = make_float2(h, l);
+    }
+    wave_allreduce<Acc>(h, l);
+    if ((t & 63) == 0)
+        wave_part[t >> 6] = make_float2(h, l);
+    __syncthreads();
+    if (t == 0) {
+        float ph = wave_part[0].x, pl = wave_part[0].y;
+#pragma unroll
+        for (int q = 1; q < kWaves; ++q)
+            Acc::merge(ph, pl, wave_part[q].x, wave_part[q].y);
+        w.partials[c] = make_float2(ph, pl);
     }
 }
 
 struct Cfg {
-    int block, unroll, grid;
+    int block, unroll;
     int64_t chunk;
 };
 
-ff_status resolve_cfg(const ff_dot_cfg *cfg, Cfg &out)
+// Default launch shapes by input kind, from sweeps on the 4096-vector batch
+// (block 64-512 threads by 4-32 elements per thread): 256 by 16 for binary32
+// dots and sums (0.80 and 0.77-0.80 of HBM peak), 256 by 8 for float-float
+// inputs (0.79-0.80; four planes in flight per element).
+template <class In> struct DefaultShape {
+    static constexpr int kBlock = 256, kUnroll = 16;
+};
+template <> struct DefaultShape<InFF> {
+    static constexpr int kBlock = 256, kUnroll = 8;
+};
+
+bool valid_unroll(int u)
 {
-    // defaults: the fastest shape on 4096 vectors of 2^6 .. 2^20 elements
-    out.block = 512;
-    out.chunk = 16384;
-    out.grid = 0;
-    out.unroll = 8;
+    return u == 1 || u == 2 || u == 4 || u == 8 || u == 16 || u == 32;
+}
+
+// A shape: block in {64, 128, 256, 512}, unroll in {1, ..., 32} (powers of
+// two), chunk = block * unroll; zero fields take the kind's default (an
+// unroll of zero with a chunk given takes chunk / block); grid is reserved
+// and must be zero.
+ff_status resolve_cfg(const ff_dot_cfg *cfg, int def_block, int def_unroll, Cfg &out)
+{
+    out.block = def_block;
+    out.unroll = def_unroll;
+    int64_t chunk = 0;
     if (cfg) {
+        if (cfg->grid != 0 || cfg->block < 0 || cfg->chunk < 0 || cfg->unroll < 0)
+            return FF_ERR_ARG;
         if (cfg->block)
             out.block = cfg->block;
-        if (cfg->chunk)
-            out.chunk = cfg->chunk;
-        if (cfg->grid)
-            out.grid = cfg->grid;
+        chunk = cfg->chunk;
         if (cfg->unroll)
             out.unroll = cfg->unroll;
+        else if (chunk)
+            out.unroll = chunk % out.block == 0 ? static_cast<int>(chunk / out.block) : 0;
     }
-    if (out.block != 256 && out.block != 512)
+    if (out.block != 64 && out.block != 128 && out.block != 256 && out.block != 512)
         return FF_ERR_ARG;
-    if (out.unroll != 1 && out.unroll != 2 && out.unroll != 4 && out.unroll != 8)
+    if (!valid_unroll(out.unroll))
         return FF_ERR_ARG;
-    if (out.chunk < 64 || out.chunk % 4 != 0)
-        return FF_ERR_ARG;
-    if (out.grid < 0)
+    out.chunk = static_cast<int64_t>(out.block) * out.unroll;
+    if (chunk && chunk != out.chunk)
         return FF_ERR_ARG;
     return FF_OK;
 }
 
-int default_grid()
+template <class In, class Acc, int BLOCK>
+void launch_chunks(int unroll, unsigned grid, hipStream_t st, const In &in, const Workspace &w,
+                   int32_t nvec)
 {
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        cus = 256;  // MI355X's count when the query fails
-    return 8 * (cus > 0 ? cus : 256);
-}
-
-template <class In, class Acc, int BLOCK, int UNROLL>
-void launch_partials(bool vec, int grid, hipStream_t st, const In &in, const Workspace &w,
-                     int32_t nvec)
-{
-    if (vec)
-        hipLaunchKernelGGL((dot_partials<In, Acc, BLOCK, UNROLL, true>), dim3(grid), dim3(BLOCK),
-                           0, st, in, w, nvec);
-    else
-        hipLaunchKernelGGL((dot_partials<In, Acc, BLOCK, 1, false>), dim3(grid), dim3(BLOCK), 0,
-                           st, in, w, nvec);
+    switch (unroll) {
+    case 1: hipLaunchKernelGGL((dot_chunks<In, Acc, BLOCK, 1>), dim3(grid), dim3(BLOCK), 0, st, in, w, nvec); break;
+    case 2: hipLaunchKernelGGL((dot_chunks<In, Acc, BLOCK, 2>), dim3(grid), dim3(BLOCK), 0, st, in, w, nvec); break;
+    case 4: hipLaunchKernelGGL((dot_chunks<In, Acc, BLOCK, 4>), dim3(grid), dim3(BLOCK), 0, st, in, w, nvec); break;
+    case 8: hipLaunchKernelGGL((dot_chunks<In, Acc, BLOCK, 8>), dim3(grid), dim3(BLOCK), 0, st, in, w, nvec); break;
+    case 16: hipLaunchKernelGGL((dot_chunks<In, Acc, BLOCK, 16>), dim3(grid), dim3(BLOCK), 0, st, in, w, nvec); break;
+    default: hipLaunchKernelGGL((dot_chunks<In, Acc, BLOCK, 32>), dim3(grid), dim3(BLOCK), 0, st, in, w, nvec); break;
+    }
 }
 
 template <class In, class Acc = AccFF>
-ff_status dot_batched_entry(const In &in, bool vec, const int64_t *offsets, int32_t nvec,
-                            int64_t total, const ff_dot_cfg *cfg_in, void *ws, size_t ws_bytes,
-                            float *out_hi, float *out_lo, void *stream_ptr)
+ff_status dot_batched_entry(const In &in, const int64_t *offsets, int32_t nvec, int64_t total,
+                            const ff_dot_cfg *cfg_in, void *ws, size_t ws_bytes, float *out_hi,
+                            float *out_lo, void *stream_ptr)
 {
     Cfg cfg;
-    const ff_status cs = resolve_cfg(cfg_in, cfg);
+    const ff_status cs =
+        resolve_cfg(cfg_in, DefaultShape<In>::kBlock, DefaultShape<In>::kUnroll, cfg);
     if (cs != FF_OK)
         return cs;
     if (nvec == 0)
@@ -508,35 +468,31 @@ ff_status dot_batched_entry(const In &in, bool vec, const int64_t *offsets, int3
         return FF_ERR_ALIGN;
     if (ws_bytes < workspace_bytes(total, nvec, cfg.chunk))
         return FF_ERR_WORKSPACE;
-    hipStream_t st = ffh::as_stream(stream_ptr);
     const Workspace w = carve(ws, total, nvec, cfg.chunk);
-    const int grid = cfg.grid ? cfg.grid : default_grid();
+    if (w.cap > INT32_MAX)
+        return FF_ERR_SIZE;
+    hipStream_t st = ffh::as_stream(stream_ptr);
     const unsigned wave_blocks = static_cast<unsigned>(ffh::cdiv(nvec, 4));
+    const unsigned grid = static_cast<unsigned>(w.cap);
     hipLaunchKernelGGL(dot_plan, dim3(1), dim3(kPlanBlock), 0, st, offsets, nvec, total,
                        cfg.chunk, w);
     hipLaunchKernelGGL(dot_ranges, dim3(wave_blocks), dim3(256), 0, st, offsets, nvec, total,
                        cfg.chunk, w);
-#define FF_DOT_LAUNCH(B, U) launch_partials<In, Acc, B, U>(vec, grid, st, in, w, nvec)
-    if (cfg.block == 256) {
-        switch (cfg.unroll) {
-        case 1: FF_DOT_LAUNCH(256, 1); break;
-        case 2: FF_DOT_LAUNCH(256, 2); break;
-        case 4: FF_DOT_LAUNCH(256, 4); break;
-        default: FF_DOT_LAUNCH(256, 8); break;
-        }
-    } else {
-        switch (cfg.unroll) {
-        case 1: FF_DOT_LAUNCH(512, 1); break;
-        case 2: FF_DOT_LAUNCH(512, 2); break;
-        case 4: FF_DOT_LAUNCH(512, 4); break;
-        default: FF_DOT_LAUNCH(512, 8); break;
-        }
+    switch (cfg.block) {
+    case 64: launch_chunks<In, Acc, 64>(cfg.unroll, grid, st, in, w, nvec); break;
+    case 128: launch_chunks<In, Acc, 128>(cfg.unroll, grid, st, in, w, nvec); break;
+    case 256: launch_chunks<In, Acc, 256>(cfg.unroll, grid, st, in, w, nvec); break;
+    default: launch_chunks<In, Acc, 512>(cfg.unroll, grid, st, in, w, nvec); break;
     }
-#undef FF_DOT_LAUNCH
     hipLaunchKernelGGL(dot_combine<Acc>, dim3(wave_blocks), dim3(256), 0, st, nvec, w, out_hi,
                        out_lo);
     return ffh::launch_status();
 }
+
+// The smallest default chunk over the input kinds: a workspace sized for it
+// serves every kind's default shape.
+constexpr int64_t kSmallestDefaultChunk =
+    static_cast<int64_t>(DefaultShape<InFF>::kBlock) * DefaultShape<InFF>::kUnroll;
 
 } // namespace ffk
 
@@ -546,8 +502,11 @@ extern "C" {
 
 size_t ff_dot_batched_workspace_size(int64_t total_len, int32_t nvec, const ff_dot_cfg *cfg)
 {
+    // resolved with the smallest default chunk of the input kinds: enough for
+    // every entry point called with this cfg
     Cfg c;
-    if (total_len < 0 || nvec < 0 || resolve_cfg(cfg, c) != FF_OK)
+    if (total_len < 0 || nvec < 0 ||
+        resolve_cfg(cfg, DefaultShape<InFF>::kBlock, DefaultShape<InFF>::kUnroll, c) != FF_OK)
         return 0;
     return workspace_bytes(total_len, nvec, c.chunk);
 }
@@ -562,9 +521,8 @@ ff_status ff_dot_batched(const float *x, const float *y, const int64_t *offsets,
         return FF_ERR_NULL;
     if (!ffh::aligned(x, 4) || !ffh::aligned(y, 4))
         return FF_ERR_ALIGN;
-    const bool vec = ffh::aligned(x, 16) && ffh::aligned(y, 16);
-    return dot_batched_entry(InF32{x, y}, vec, offsets, nvec, total_len, cfg, ws, ws_bytes,
-                             out_hi, out_lo, stream);
+    return dot_batched_entry(InF32{x, y}, offsets, nvec, total_len, cfg, ws, ws_bytes, out_hi,
+                             out_lo, stream);
 }
 
 ff_status ff_dot_ff_batched(const float *x_hi, const float *x_lo, const float *y_hi,
@@ -577,13 +535,10 @@ ff_status ff_dot_ff_batched(const float *x_hi, const float *x_lo, const float *y
     if (total_len > 0 && (!x_hi || !x_lo || !y_hi || !y_lo))
         return FF_ERR_NULL;
     const void *planes[4] = {x_hi, x_lo, y_hi, y_lo};
-    bool vec = true;
-    for (const void *p : planes) {
+    for (const void *p : planes)
         if (!ffh::aligned(p, 4))
             return FF_ERR_ALIGN;
-        vec = vec && ffh::aligned(p, 16);
-    }
-    return dot_batched_entry(InFF{x_hi, x_lo, y_hi, y_lo}, vec, offsets, nvec, total_len, cfg, ws,
+    return dot_batched_entry(InFF{x_hi, x_lo, y_hi, y_lo}, offsets, nvec, total_len, cfg, ws,
                              ws_bytes, out_hi, out_lo, stream);
 }
 
@@ -597,8 +552,8 @@ ff_status ff_sum_batched(const float *x, const int64_t *offsets, int32_t nvec, i
         return FF_ERR_NULL;
     if (!ffh::aligned(x, 4))
         return FF_ERR_ALIGN;
-    return dot_batched_entry(InSumF32{x}, ffh::aligned(x, 16), offsets, nvec, total_len, cfg, ws,
-                             ws_bytes, out_hi, out_lo, stream);
+    return dot_batched_entry(InSumF32{x}, offsets, nvec, total_len, cfg, ws, ws_bytes, out_hi,
+                             out_lo, stream);
 }
 
 ff_status ff_sum_ff_batched(const float *x_hi, const float *x_lo, const int64_t *offsets,
@@ -611,8 +566,7 @@ ff_status ff_sum_ff_batched(const float *x_hi, const float *x_lo, const int64_t 
         return FF_ERR_NULL;
     if (!ffh::aligned(x_hi, 4) || !ffh::aligned(x_lo, 4))
         return FF_ERR_ALIGN;
-    const bool vec = ffh::aligned(x_hi, 16) && ffh::aligned(x_lo, 16);
-    return dot_batched_entry(InSumFF{x_hi, x_lo}, vec, offsets, nvec, total_len, cfg, ws, ws_bytes,
+    return dot_batched_entry(InSumFF{x_hi, x_lo}, offsets, nvec, total_len, cfg, ws, ws_bytes,
                              out_hi, out_lo, stream);
 }
 
@@ -626,8 +580,7 @@ ff_status ff_dot2_batched(const float *x, const float *y, const int64_t *offsets
         return FF_ERR_NULL;
     if (!ffh::aligned(x, 4) || !ffh::aligned(y, 4))
         return FF_ERR_ALIGN;
-    const bool vec = ffh::aligned(x, 16) && ffh::aligned(y, 16);
-    return dot_batched_entry<InF32, AccComp>(InF32{x, y}, vec, offsets, nvec, total_len, cfg, ws,
+    return dot_batched_entry<InF32, AccComp>(InF32{x, y}, offsets, nvec, total_len, cfg, ws,
                                              ws_bytes, out_hi, out_lo, stream);
 }
 
@@ -641,9 +594,8 @@ ff_status ff_sum2_batched(const float *x, const int64_t *offsets, int32_t nvec,
         return FF_ERR_NULL;
     if (!ffh::aligned(x, 4))
         return FF_ERR_ALIGN;
-    return dot_batched_entry<InSumF32, AccComp>(InSumF32{x}, ffh::aligned(x, 16), offsets, nvec,
-                                                total_len, cfg, ws, ws_bytes, out_hi, out_lo,
-                                                stream);
+    return dot_batched_entry<InSumF32, AccComp>(InSumF32{x}, offsets, nvec, total_len, cfg, ws,
+                                                ws_bytes, out_hi, out_lo, stream);
 }
 
 } // extern "C"
@@ -700,7 +652,8 @@ ff_status ff_dot_batched_noalloc(const float *x, const float *y, const int64_t *
     if (!ffh::aligned(x, 4) || !ffh::aligned(y, 4))
         return FF_ERR_ALIGN;
     Cfg c;
-    const ff_status cs = resolve_cfg(cfg, c);
+    const ff_status cs =
+        resolve_cfg(cfg, DefaultShape<InF32>::kBlock, DefaultShape<InF32>::kUnroll, c);
     if (cs != FF_OK)
         return cs;
     if (nvec == 0)
@@ -715,8 +668,7 @@ ff_status ff_dot_batched_noalloc(const float *x, const float *y, const int64_t *
     const ff_status ss = scratch_on_current_device(&ws);
     if (ss != FF_OK)
         return ss;
-    const bool vec = ffh::aligned(x, 16) && ffh::aligned(y, 16);
-    return dot_batched_entry(InF32{x, y}, vec, offsets, nvec, total_len, cfg, ws,
+    return dot_batched_entry(InF32{x, y}, offsets, nvec, total_len, cfg, ws,
                              FF_NOALLOC_SCRATCH_BYTES, out_hi, out_lo, stream);
 }
 
@@ -729,14 +681,8 @@ ff_status ff_dot_batched_autotune(const float *x, const float *y, const int64_t 
         return FF_ERR_NULL;
     if (reps < 1)
         return FF_ERR_ARG;
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return ffh::hip_failure(hipGetLastError());
-    static const int kBlocks[] = {256, 512};
-    static const int kUnrolls[] = {1, 2, 4, 8};
-    static const int kChunks[] = {1024, 2048, 4096, 8192, 16384, 32768};
-    static const int kPerCu[] = {2, 4, 8, 16};
+    static const int kBlocks[] = {64, 128, 256, 512};
+    static const int kUnrolls[] = {4, 8, 16, 32};
     hipStream_t st = ffh::as_stream(stream);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess)
@@ -749,38 +695,36 @@ ff_status ff_dot_batched_autotune(const float *x, const float *y, const int64_t 
     ff_status status = FF_OK;
     float best_time = -1.0f;
     for (int blk : kBlocks)
-        for (int un : kUnrolls)
-            for (int ch : kChunks)
-                for (int pc : kPerCu) {
-                    ff_dot_cfg c{blk, ch, pc * cus, un};
-                    if (ff_dot_batched_workspace_size(total_len, nvec, &c) > ws_bytes)
-                        continue;
-                    // one untimed launch, then reps timed launches
-                    status = ff_dot_batched(x, y, offsets, nvec, total_len, &c, ws, ws_bytes,
-                                            out_hi, out_lo, stream);
-                    if (status != FF_OK)
-                        goto done;
-                    if (hipEventRecord(e0, st) != hipSuccess) {
-                        status = ffh::hip_failure(hipGetLastError());
-                        goto done;
-                    }
-                    for (int r = 0; r < reps && status == FF_OK; ++r)
-                        status = ff_dot_batched(x, y, offsets, nvec, total_len, &c, ws, ws_bytes,
-                                                out_hi, out_lo, stream);
-                    if (status != FF_OK)
-                        goto done;
-                    float ms = 0.0f;
-                    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                        status = ffh::hip_failure(hipGetLastError());
-                        goto done;
-                    }
-                    ms /= reps;
-                    if (best_time < 0.0f || ms < best_time) {
-                        best_time = ms;
-                        *best = c;
-                    }
-                }
+        for (int un : kUnrolls) {
+            ff_dot_cfg c{blk, blk * un, 0, un};
+            if (ff_dot_batched_workspace_size(total_len, nvec, &c) > ws_bytes)
+                continue;
+            // one untimed launch, then reps timed launches
+            status = ff_dot_batched(x, y, offsets, nvec, total_len, &c, ws, ws_bytes, out_hi,
+                                    out_lo, stream);
+            if (status != FF_OK)
+                goto done;
+            if (hipEventRecord(e0, st) != hipSuccess) {
+                status = ffh::hip_failure(hipGetLastError());
+                goto done;
+            }
+            for (int r = 0; r < reps && status == FF_OK; ++r)
+                status = ff_dot_batched(x, y, offsets, nvec, total_len, &c, ws, ws_bytes, out_hi,
+                                        out_lo, stream);
+            if (status != FF_OK)
+                goto done;
+            float ms = 0.0f;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                status = ffh::hip_failure(hipGetLastError());
+                goto done;
+            }
+            ms /= reps;
+            if (best_time < 0.0f || ms < best_time) {
+                best_time = ms;
+                *best = c;
+            }
+        }
     if (best_time < 0.0f)
         status = FF_ERR_WORKSPACE;
     *best_ms = best_time;

@@ -201,12 +201,15 @@ def test_dot_workspace_size():
     assert size(0, 0) > 0 or size(0, 0) == 0
     assert size(1 << 20, 10) > 0
     assert size(-1, 10) == 0 and size(10, -1) == 0
-    assert size(100, 3, (0, 0, 0, 3)) == 0          # unroll must be 1, 2, 4 or 8
-    assert size(100, 3, (0, 60, 0, 0)) == 0         # chunk >= 64
-    assert size(100, 3, (0, 66, 0, 0)) == 0         # chunk multiple of 4
-    assert size(100, 3, (128, 0, 0, 0)) == 0        # block 256 or 512
+    assert size(100, 3, (0, 0, 0, 3)) == 0          # unroll: a power of two up to 32
+    assert size(100, 3, (0, 0, 0, 64)) == 0
+    assert size(100, 3, (0, 60, 0, 0)) == 0         # chunk must be block * unroll
+    assert size(100, 3, (256, 1024, 0, 8)) == 0
+    assert size(100, 3, (96, 0, 0, 0)) == 0         # block 64, 128, 256 or 512
+    assert size(100, 3, (256, 0, 7, 0)) == 0        # grid reserved: zero
+    assert size(100, 3, (0, 1024, 0, 0)) > 0        # chunk alone sets unroll = chunk / block
     # grows with the chunk count (total / chunk + nvec partials)
-    assert size(1 << 24, 4, (256, 64, 0, 1)) > size(1 << 24, 4, (256, 16384, 0, 1))
+    assert size(1 << 24, 4, (64, 256, 0, 4)) > size(1 << 24, 4, (512, 16384, 0, 32))
 
 
 @pytest.mark.parametrize("name", ["ff_dot_batched", "ff_dot_ff_batched", "ff_dot2_batched",
@@ -262,13 +265,16 @@ def test_dot_noalloc_validation():
     assert call(ol=None) == ERR_NULL
     assert call(y=y + 2) == ERR_ALIGN
     assert call(offs=offs + 4) == ERR_ALIGN
-    # the batch must fit the static scratch: 4 MiB
-    limit = 4 << 20
-    fits = ff.ff_dot_batched_workspace_size(2_773_499_903, 4096)
-    assert fits <= limit < ff.ff_dot_batched_workspace_size(2_773_499_904 + (1 << 14), 4096)
+    # the batch must fit the static scratch: 16 MiB (default shape: 4096 elements
+    # per chunk)
+    limit = 16 << 20
+    shape = (256, 4096, 0, 16)
+    assert ff.ff_dot_batched_workspace_size(2_840_858_623, 4096, shape) <= limit
+    assert ff.ff_dot_batched_workspace_size(2_840_858_623 + 4096, 4096, shape) > limit
     assert call(nvec=4096, total=(1 << 14) * (1 << 20)) == ERR_WS
-    assert call(nvec=300_000, total=1000) == ERR_WS   # too many vectors
-    assert call(nvec=8, total=1 << 40, cfg=(0, 64, 0, 0)) == ERR_WS
+    assert call(nvec=1_000_000, total=1000) == ERR_WS   # too many vectors
+    assert call(nvec=8, total=1 << 40, cfg=(64, 256, 0, 4)) == ERR_WS
+    assert call(cfg=(256, 0, 3, 0)) == ERR_ARG
 
 
 def test_matvec_validation():

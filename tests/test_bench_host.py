@@ -94,5 +94,5 @@ def test_default_arguments_measure_one_gpu_on_the_full_workload():
     assert a.gpus == 1 and a.steps > 0 and a.warmup >= 0
     assert a.log2n == 28 and a.seed == 115002 and a.dot_cfg is None
     assert not a.no_cpu_baseline and not a.no_secondary
-    b = bench.parse_args(["--steps", "5", "--warmup", "2", "--dot-cfg", "512,8192,4096,8"])
-    assert (b.steps, b.warmup, b.dot_cfg) == (5, 2, "512,8192,4096,8")
+    b = bench.parse_args(["--steps", "5", "--warmup", "2", "--dot-cfg", "256,4096,0,16"])
+    assert (b.steps, b.warmup, b.dot_cfg) == (5, 2, "256,4096,0,16")

@@ -36,16 +36,18 @@ def _announce(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def tree_depth(lengths, cfg):
-    """Longest chain of Add22s behind a result: a lane's accumulator over its
-    share of a chunk (one wavefront per chunk, 4 accumulators per lane, plus
-    one edge element), 2 merges, the 6-level butterfly, then the chunk
-    partials lane-strided, a second butterfly, and slack."""
-    _, chunk, _, _ = cfg
-    chunk = chunk or 16384
-    per_lane = math.ceil(chunk / (4 * 64)) + 1
+def tree_depth(lengths, cfg, default=(256, 16)):
+    """Longest chain of Add22s behind a result: a thread's `unroll` terms in
+    order, the 6-level butterfly, the wavefronts of the workgroup in order,
+    then the chunk partials lane-strided, a second butterfly, and slack.
+    `default` is the entry point's (block, unroll) for zero fields."""
+    block, chunk, _, unroll = cfg
+    block = block or default[0]
+    if not unroll:
+        unroll = chunk // block if chunk else default[1]
+    chunk = block * unroll
     nch = max(1, max(math.ceil(int(n) / chunk) for n in lengths))
-    return per_lane + 2 + 6 + math.ceil(nch / 64) + 6 + 2
+    return unroll + 6 + block // 64 + math.ceil(nch / 64) + 6 + 2
 
 
 def check_against_exact(x, y, offs, got, cfg, label, target=TWO_M44):
@@ -68,8 +70,8 @@ def check_against_exact(x, y, offs, got, cfg, label, target=TWO_M44):
     return worst
 
 
-CFGS = [(0, 0, 0, 0), (256, 64, 0, 1), (512, 1000, 7, 4), (256, 4096, 64, 2), (512, 16384, 0, 2),
-        (256, 16384, 2048, 4)]
+CFGS = [(0, 0, 0, 0), (64, 256, 0, 4), (128, 1024, 0, 0), (256, 0, 0, 2), (512, 16384, 0, 32),
+        (0, 2048, 0, 0)]
 
 
 @pytest.mark.parametrize("cfg", CFGS, ids=[str(c) for c in CFGS])
@@ -119,12 +121,12 @@ def test_integer_data_is_exact():
         assert frac(got[0, v]) + frac(got[1, v]) == want
 
 
-def test_unaligned_inputs_take_the_element_path():
+def test_unaligned_inputs():
     x, y, offs = fi.batched_dot(99, nvec=40, max_total=200000)
     xb = torch.cat([torch.zeros(1), x]).cuda()[1:]
     yb = torch.cat([torch.zeros(3), y]).cuda()[3:]
-    got = _ff().ff_dot_batched(xb, yb, offs.cuda(), cfg=(256, 1024, 0, 1))
-    check_against_exact(x, y, offs, got, (256, 1024, 0, 1), "unaligned")
+    got = _ff().ff_dot_batched(xb, yb, offs.cuda(), cfg=(256, 1024, 0, 4))
+    check_against_exact(x, y, offs, got, (256, 1024, 0, 4), "unaligned")
 
 
 def test_empty_batch_and_empty_vectors():
@@ -209,7 +211,8 @@ def test_autotuner_returns_a_valid_fast_shape(tmp_path, monkeypatch):
     autotune._MEMO = None
     x, y, offs = fi.batched_dot(115003, nvec=512, max_total=1 << 24, device="cuda")
     cfg = autotune.dot_cfg(x, y, offs)
-    assert cfg[0] in (256, 512) and cfg[3] in (1, 2, 4, 8) and cfg[1] % 4 == 0
+    assert cfg[0] in (64, 128, 256, 512) and cfg[3] in (4, 8, 16, 32)
+    assert cfg[1] == cfg[0] * cfg[3] and cfg[2] == 0
     assert (tmp_path / "tune.json").exists()
     autotune._MEMO = None
     assert autotune.dot_cfg(x, y, offs, search=False) == cfg      # served from the file
