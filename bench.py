@@ -166,9 +166,11 @@ def _oracle_parallel(tasks) -> tuple[float, int]:
 
 def _baseline(value_mt, threads, value_st, unit, sample) -> dict:
     """The cpu_baseline object: the oracle on `threads` host threads, with the
-    single-threaded rate of the same sample beside it."""
+    single-threaded rate of the same sample and the host's total logical CPU
+    count beside it."""
     return {"value": value_mt, "unit": unit, "cores": threads, "kind": "oracle",
-            "sample": sample, "single_thread_value": value_st, "host_cpu": _host_cpu()}
+            "sample": sample, "single_thread_value": value_st, "host_cpu": _host_cpu(),
+            "host_cores_total": os.cpu_count()}
 
 
 def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
@@ -387,11 +389,17 @@ def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
     A = fi.gaussian_ff((m, m), 115005, device=dev)
     xv = fi.gaussian_ff((m,), 115006, device=dev)
     g = torch.stack([fi.gaussian_f32((m,), 115007, device=dev), torch.zeros(m, device=dev)])
+    # outputs and workspace allocated once, outside the timed calls
+    yv, dA, dxv = ff.ff_empty((m,), device=dev), ff.ff_empty((m, m), device=dev), ff.ff_empty((m,), device=dev)
     mv = {}
     for name, algo in (("fast", ff.MATVEC_FAST), ("plain", ff.MATVEC_PLAIN)):
-        fwd = _time_launches(lambda: ff.ff_matvec(A, xv, algo=algo, stream=stream), 10, stream)
-        bwd = _time_launches(lambda: ff.ff_matvec_backward(A, xv, g, algo=algo, stream=stream),
+        wsm = torch.empty(max(ff.ff_matvec_backward_workspace_size(m, m, algo), 16),
+                          dtype=torch.uint8, device=dev)
+        fwd = _time_launches(lambda: ff.ff_matvec(A, xv, algo=algo, out=yv, stream=stream), 10, stream)
+        bwd = _time_launches(lambda: ff.ff_matvec_backward(A, xv, g, algo=algo, dA_out=dA, dx_out=dxv,
+                                                           workspace=wsm, stream=stream),
                              5, stream)
+        del wsm
         mv[name] = {"forward_ms": round(fwd, 4), "backward_ms": round(bwd, 4),
                     "forward_GB/s": round(8 * m * m / (fwd * 1e-3) / 1e9, 1),
                     "backward_GB/s": round(16 * m * m / (bwd * 1e-3) / 1e9, 1)}
@@ -410,7 +418,7 @@ def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
             f"all {r} rows of y = A x (sequential Add22 of Mul22 terms), rows in {4 * th} "
             f"pieces, C oracle on {th} host threads, {dtp:.2f} s ({dt:.2f} s on one)")
     out["matvec_8192"] = mv
-    del A, xv, g
+    del A, xv, g, yv, dA, dxv
     torch.cuda.empty_cache()
 
     n = 1 << 28

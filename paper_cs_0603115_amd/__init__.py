@@ -30,7 +30,8 @@ __all__ = [
     "ff_dot_batched", "ff_dot_batched_noalloc", "ff_dot_ff_batched",
     "ff_dot_batched_workspace_size",
     "ff_sum_batched", "ff_sum_ff_batched", "ff_dot2_batched", "ff_sum2_batched",
-    "ff_matvec", "ff_matvec_backward", "ff_dot_backward", "ff_dot_batched_backward",
+    "ff_matvec", "ff_matvec_backward", "ff_matvec_backward_workspace_size", "ff_dot_backward",
+    "ff_dot_batched_backward",
     "MATVEC_FAST", "MATVEC_PLAIN",
     "ff_gemm", "ff_gemm_workspace_size", "GEMM_FMA_LOOP", "GEMM_SLICED_BF16", "GEMM_SLICED_I8",
     "ff_empty", "ff_zeros", "ff_from_f64", "ff_to_f64",
@@ -627,20 +628,37 @@ def ff_matvec(A: torch.Tensor, x: torch.Tensor, algo: int = MATVEC_FAST, out=Non
     return out
 
 
+def ff_matvec_backward_workspace_size(M: int, N: int, algo: int = MATVEC_FAST) -> int:
+    """Workspace bytes ff_matvec_backward needs for an M x N matrix."""
+    return int(lib.ff_matvec_backward_workspace_size(M, N, int(algo)))
+
+
 @_on_stream
 def ff_matvec_backward(A: torch.Tensor, x: torch.Tensor, g: torch.Tensor, want_dA: bool = True,
-                       want_dx: bool = True, algo: int = MATVEC_FAST, stream=None):
+                       want_dx: bool = True, algo: int = MATVEC_FAST, dA_out=None, dx_out=None,
+                       workspace=None, stream=None):
     """Backward pass of y = A x for the upstream float-float gradient g (2, M):
-    returns (dA, dx) = (g x^T, A^T g); a gradient not wanted is None."""
+    returns (dA, dx) = (g x^T, A^T g); a gradient not wanted is None.
+    dA_out (2, M, N) and dx_out (2, N) receive the gradients when given;
+    workspace (uint8, at least ff_matvec_backward_workspace_size bytes)
+    replaces the per-call allocation."""
     M, N, lda = _check_matrix(A)
     _check_ff(x, "x")
     _check_ff(g, "g")
     if x.shape != (2, N) or g.shape != (2, M):
         raise ValueError("shape mismatch between A, x and g")
-    dA = ff_empty((M, N), device=A.device) if want_dA else None
-    dx = ff_empty((N,), device=A.device) if want_dx else None
-    nbytes = int(lib.ff_matvec_backward_workspace_size(M, N, int(algo))) if want_dx else 0
-    ws = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=A.device)
+    dA = (ff_empty((M, N), device=A.device) if dA_out is None else dA_out) if want_dA else None
+    dx = (ff_empty((N,), device=A.device) if dx_out is None else dx_out) if want_dx else None
+    if dA is not None:
+        _check_ff(dA, "dA_out")
+        if dA.shape != (2, M, N):
+            raise ValueError(f"dA_out must have shape (2, {M}, {N})")
+    if dx is not None:
+        _check_ff(dx, "dx_out")
+        if dx.shape != (2, N):
+            raise ValueError(f"dx_out must have shape (2, {N})")
+    nbytes = ff_matvec_backward_workspace_size(M, N, algo) if want_dx else 0
+    ws = _workspace(max(nbytes, 16), A.device, workspace)
     Ah, Al = _planes(A)
     xh, xl = _planes(x)
     gh, gl = _planes(g)

@@ -76,15 +76,25 @@ def check_cols_exact(A, g, dx, label, cols=None):
     return worst
 
 
-def check_dA_bits(x, g, dA, label, rows=None):
+def check_dA_bits(x, g, dA, label, rows=None, block=256):
+    """dA[i, j] = Mul22(g_i, x_j) bit for bit, in blocks of `block` rows (the
+    oracle runs on one flattened block at a time)."""
     xn, gn, dn = x.cpu().numpy(), g.cpu().numpy(), dA.cpu().numpy()
     M, N = dn.shape[1], dn.shape[2]
-    for i in (range(M) if rows is None else rows):
-        gh = np.full(N, gn[0, i], np.float32)
-        gl = np.full(N, gn[1, i], np.float32)
-        rh, rl = oracle.mul22(gh, gl, xn[0], xn[1])
-        assert same_bits(dn[0, i], rh) and same_bits(dn[1, i], rl), (label, i,
-                                                                      mismatch_report(dn[0, i], rh))
+    rows = np.arange(M) if rows is None else np.asarray(rows)
+    for b0 in range(0, rows.size, block):
+        rb = rows[b0:b0 + block]
+        gh = np.repeat(gn[0, rb], N)
+        gl = np.repeat(gn[1, rb], N)
+        rh, rl = oracle.mul22(gh, gl, np.tile(xn[0], rb.size), np.tile(xn[1], rb.size))
+        rh, rl = rh.reshape(rb.size, N), rl.reshape(rb.size, N)
+        got_h, got_l = dn[0, rb], dn[1, rb]
+        if not (same_bits(got_h, rh) and same_bits(got_l, rl)):
+            bad = int(rb[np.flatnonzero(((got_h.view(np.uint32) != rh.view(np.uint32)) |
+                                         (got_l.view(np.uint32) != rl.view(np.uint32))).any(axis=1))[0]])
+            i = int(np.flatnonzero(rb == bad)[0])
+            raise AssertionError((label, bad, "hi: " + mismatch_report(got_h[i], rh[i]),
+                                  "lo: " + mismatch_report(got_l[i], rl[i])))
 
 
 SHAPES = [(1, 1), (3, 5), (64, 1024), (300, 517), (129, 4096), (70, 63)]
@@ -139,6 +149,37 @@ def test_backward_partial_requests_and_padded_rows():
     dA, dx = ff.ff_matvec_backward(A, x, g, want_dx=False)
     assert dx is None
     check_dA_bits(x, g, dA, "dA only")
+
+
+def test_backward_into_preallocated_outputs_and_workspace():
+    """dA_out, dx_out and workspace are written in place and give the bits
+    of the allocating call; outputs and workspaces of the wrong size are
+    refused before any launch."""
+    ff = _ff()
+    M, N = 300, 517
+    A = fi.gaussian_ff((M, N), 34).cuda()
+    x = fi.gaussian_ff((N,), 35).cuda()
+    g = fi.gaussian_ff((M,), 36).cuda()
+    for algo in (ff.MATVEC_FAST, ff.MATVEC_PLAIN):
+        want_dA, want_dx = ff.ff_matvec_backward(A, x, g, algo=algo)
+        dA = torch.full((2, M, N), float("nan"), device="cuda")
+        dx = torch.full((2, N), float("nan"), device="cuda")
+        ws = torch.empty(max(ff.ff_matvec_backward_workspace_size(M, N, algo), 16),
+                         dtype=torch.uint8, device="cuda")
+        for _ in range(2):
+            rA, rx = ff.ff_matvec_backward(A, x, g, algo=algo, dA_out=dA, dx_out=dx, workspace=ws)
+            assert rA is dA and rx is dx
+            assert torch.equal(dA.view(torch.int32), want_dA.view(torch.int32))
+            assert torch.equal(dx.view(torch.int32), want_dx.view(torch.int32))
+    nbytes = ff.ff_matvec_backward_workspace_size(M, N)
+    if nbytes > 16:
+        with pytest.raises(ValueError):
+            ff.ff_matvec_backward(A, x, g, workspace=torch.empty(nbytes - 1, dtype=torch.uint8,
+                                                                  device="cuda"))
+    with pytest.raises(ValueError):
+        ff.ff_matvec_backward(A, x, g, dA_out=ff.ff_empty((M, N + 1), device="cuda"))
+    with pytest.raises(ValueError):
+        ff.ff_matvec_backward(A, x, g, dx_out=ff.ff_empty((N - 1,), device="cuda"))
 
 
 @pytest.mark.parametrize("n", [1, 4095, 4097, 100003])
@@ -242,9 +283,8 @@ def test_full_size_8192_matvec_and_backward():
     _announce("[gpu] matvec full size: checking y (all rows)")
     wy = check_rows_exact(A.detach(), x.detach(), y.detach(), "full y")
     _announce(f"  y worst normwise log2 error {wy:.1f}")
-    _announce("[gpu] matvec full size: checking dA bits (sampled rows) and dx (all columns)")
-    rows = list(range(0, M, 97)) + [M - 1]
-    check_dA_bits(x.detach(), w, A.grad, "full dA", rows=rows)
+    _announce("[gpu] matvec full size: checking dA bits (all 8192 rows) and dx (all columns)")
+    check_dA_bits(x.detach(), w, A.grad, "full dA")
     wx = check_cols_exact(A.detach(), w, x.grad, "full dx")
     _announce(f"  dx worst normwise log2 error {wx:.1f}")
     # FP64 central finite differences of L in 64 seeded coordinates of x and
