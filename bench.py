@@ -93,7 +93,8 @@ def parse_args(argv=None):
                         "skips the autotuner (so that a profile holds only launches of this "
                         "shape)")
     p.add_argument("--no-secondary", action="store_true",
-                   help="skip the batched-dot, Horner, GEMM, matvec and conversion measurements")
+                   help="skip the batched-dot, Horner, GEMM, matvec, conversion and single-dot "
+                        "backward measurements")
     return p.parse_args(argv)
 
 
@@ -282,17 +283,13 @@ def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
     gvec = torch.ones((2, offs.numel() - 1), device=dev)
     gvec[1].zero_()
     dxb, dyb = ff.ff_empty((total,), device=dev), ff.ff_empty((total,), device=dev)
-    gh, gl = gvec[0].data_ptr(), gvec[1].data_ptr()
-
-    def dot_bwd():
-        from paper_cs_0603115_amd import _lib
-        _lib.check("ff_dot_batched_backward", ff.lib.ff_dot_batched_backward(
-            gh, gl, offs.data_ptr(), offs.numel() - 1, total, x.data_ptr(), None, y.data_ptr(),
-            None, dxb[0].data_ptr(), dxb[1].data_ptr(), dyb[0].data_ptr(), dyb[1].data_ptr(),
-            stream.cuda_stream))
-    msb = _time_launches(dot_bwd, 10, stream)
+    wsb = torch.empty(ff.ff_dot_batched_backward_workspace_size(total), dtype=torch.uint8,
+                      device=dev)
+    msb = _time_launches(lambda: ff.ff_dot_batched_backward(gvec, x, y, offs, dx_out=dxb, dy_out=dyb,
+                                                            workspace=wsb, stream=stream),
+                         10, stream)
     gbsb = 24 * total / (msb * 1e-3) / 1e9
-    del dxb, dyb, gvec
+    del dxb, dyb, gvec, wsb
     # the other entry points of the family on the same batch, each with its
     # default launch shape: float-float inputs (16 B per element), sums of
     # binary32 (4 B) and of float-float (8 B) terms
@@ -435,6 +432,19 @@ def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
                       "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     out["conversions_2p28"] = conv
     del xd, pair, back
+    torch.cuda.empty_cache()
+
+    log("[bench] single-dot backward at N = 2^28 (float-float x and y)")
+    xs = fi.gaussian_ff((n,), 115061, device=dev)
+    ys = fi.gaussian_ff((n,), 115062, device=dev)
+    gs = torch.tensor([[0.75], [2.0 ** -30]], dtype=torch.float32, device=dev)
+    dxs, dys = ff.ff_empty((n,), device=dev), ff.ff_empty((n,), device=dev)
+    ms = _time_launches(lambda: ff.ff_dot_backward(gs, xs, ys, dx_out=dxs, dy_out=dys,
+                                                   stream=stream), 10, stream, warmup=2)
+    gbs = 32 * n / (ms * 1e-3) / 1e9                    # x, y read; dx, dy written: 4 planes each
+    out["dot_backward_2p28"] = {"ms": round(ms, 4), "GB/s": round(gbs, 1),
+                                "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_element": 32}
+    del xs, ys, gs, dxs, dys
     torch.cuda.empty_cache()
     return out
 

@@ -399,16 +399,23 @@ ff_status ff_dot_backward(const float *g_hi, const float *g_lo,
  * offsets: device, nvec + 1 int64, non-decreasing within [0, total_len],
  * as for the forward (violations give unspecified gradients, never accesses
  * outside the arrays: offsets are clamped to [0, total_len]).
+ * ws: device workspace of at least
+ * ff_dot_batched_backward_workspace_size(total_len) bytes, 16-byte aligned,
+ * caller-owned; it holds, per block of 256 elements, the vector owning the
+ * block's first element with its gradient (written by a first launch, read
+ * by the second), so it must not be shared by calls that may overlap.
  * Errors: FF_ERR_SIZE (nvec < 0, total_len < 0), FF_ERR_NULL, FF_ERR_ALIGN
- * (offsets not 8-byte or a plane not 4-byte aligned), FF_ERR_HIP.
- * total_len = 0 is a no-op. */
+ * (offsets not 8-byte, a plane not 4-byte or ws not 16-byte aligned),
+ * FF_ERR_WORKSPACE (ws NULL or too small), FF_ERR_HIP.
+ * total_len = 0, or no output wanted, is a no-op (ws is not read). */
+size_t ff_dot_batched_backward_workspace_size(int64_t total_len);
 ff_status ff_dot_batched_backward(const float *g_hi, const float *g_lo,
                                   const int64_t *offsets, int32_t nvec,
                                   int64_t total_len, const float *x_hi,
                                   const float *x_lo, const float *y_hi,
                                   const float *y_lo, float *dx_hi,
                                   float *dx_lo, float *dy_hi, float *dy_lo,
-                                  void *stream);
+                                  void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Matrix product C = A B                                                   */

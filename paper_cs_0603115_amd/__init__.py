@@ -31,7 +31,7 @@ __all__ = [
     "ff_dot_batched_workspace_size",
     "ff_sum_batched", "ff_sum_ff_batched", "ff_dot2_batched", "ff_sum2_batched",
     "ff_matvec", "ff_matvec_backward", "ff_matvec_backward_workspace_size", "ff_dot_backward",
-    "ff_dot_batched_backward",
+    "ff_dot_batched_backward", "ff_dot_batched_backward_workspace_size",
     "MATVEC_FAST", "MATVEC_PLAIN",
     "ff_gemm", "ff_gemm_workspace_size", "GEMM_FMA_LOOP", "GEMM_SLICED_BF16", "GEMM_SLICED_I8",
     "ff_empty", "ff_zeros", "ff_from_f64", "ff_to_f64",
@@ -89,14 +89,42 @@ def _planes(t: torch.Tensor):
     return ctypes.c_void_p(t[0].data_ptr()), ctypes.c_void_p(t[1].data_ptr())
 
 
+# Plane stride granule of ff_empty / ff_zeros, in binary32 words (4 KiB).
+PLANE_ALIGN = 1024
+
+
+def _planar(alloc, shape, device) -> torch.Tensor:
+    """A (2, *shape) float32 tensor whose two planes are each contiguous and
+    start a multiple of 4 KiB apart.  The allocator aligns the first plane,
+    so both are: a wavefront's access of 64 consecutive words of either plane
+    is then one aligned 256-byte segment.  (In a plain (2, n) tensor the low
+    plane starts 4n bytes after the high one; unless n is a multiple of 64
+    every such access straddles two segments, which cost the streaming
+    kernels up to 8 % of their rate on MI355X.)"""
+    shape = tuple(int(d) for d in shape)
+    numel = 1
+    for d in shape:
+        numel *= d
+    stride = -(-max(numel, 1) // PLANE_ALIGN) * PLANE_ALIGN
+    base = alloc(2 * stride, dtype=torch.float32, device=device)
+    inner = []
+    acc = 1
+    for d in reversed(shape):
+        inner.append(acc)
+        acc *= max(d, 1)
+    return base.as_strided((2, *shape), (stride, *reversed(inner)))
+
+
 def ff_empty(shape, device="cuda") -> torch.Tensor:
-    """Uninitialised float-float tensor of the given value shape."""
-    return torch.empty((2, *tuple(shape)), dtype=torch.float32, device=device)
+    """Uninitialised float-float tensor of the given value shape (planes
+    aligned as described in _planar)."""
+    return _planar(torch.empty, shape, device)
 
 
 def ff_zeros(shape, device="cuda") -> torch.Tensor:
-    """Float-float zeros of the given value shape."""
-    return torch.zeros((2, *tuple(shape)), dtype=torch.float32, device=device)
+    """Float-float zeros of the given value shape (planes aligned as
+    described in _planar)."""
+    return _planar(torch.zeros, shape, device)
 
 
 def _elementwise(name: str, a: torch.Tensor, b: torch.Tensor, out, stream) -> torch.Tensor:
@@ -107,7 +135,7 @@ def _elementwise(name: str, a: torch.Tensor, b: torch.Tensor, out, stream) -> to
     if a.device != b.device:
         raise ValueError(f"{name}: operands on different devices")
     if out is None:
-        out = torch.empty_like(a)
+        out = ff_empty(a.shape[1:], device=a.device)
     else:
         _check_ff(out, "out")
         if out.shape != a.shape:
@@ -673,17 +701,23 @@ def ff_matvec_backward(A: torch.Tensor, x: torch.Tensor, g: torch.Tensor, want_d
 
 @_on_stream
 def ff_dot_backward(g: torch.Tensor, x: torch.Tensor, y: torch.Tensor, want_dx: bool = True,
-                    want_dy: bool = True, stream=None):
+                    want_dy: bool = True, dx_out=None, dy_out=None, stream=None):
     """Backward pass of s = sum x_i y_i for an upstream float-float gradient
-    g (shape (2,) or (2, 1)): returns (g y, g x) (elementwise Mul22)."""
+    g (shape (2,) or (2, 1)): returns (g y, g x) (elementwise Mul22), written
+    into dx_out / dy_out (shaped like x) when given."""
     _check_ff(g, "g")
     _check_ff(x, "x")
     _check_ff(y, "y")
     if g[0].numel() != 1 or x.shape != y.shape:
         raise ValueError("g must hold one float-float value and x, y agree in shape")
     n = x[0].numel()
-    dx = torch.empty_like(x) if want_dx else None
-    dy = torch.empty_like(y) if want_dy else None
+    dx = (ff_empty(x.shape[1:], device=x.device) if dx_out is None else dx_out) if want_dx else None
+    dy = (ff_empty(y.shape[1:], device=y.device) if dy_out is None else dy_out) if want_dy else None
+    for t, name in ((dx, "dx_out"), (dy, "dy_out")):
+        if t is not None:
+            _check_ff(t, name)
+            if t.shape != x.shape or t.device != x.device:
+                raise ValueError(f"{name} must have shape {tuple(x.shape)} on {x.device}")
     g = g.reshape(2, 1).contiguous()
     gh, gl = _planes(g)
     xh, xl = _planes(x)
@@ -709,15 +743,23 @@ def _ff_or_f32_planes(t: torch.Tensor, name: str):
     return hi, lo, t.shape[1]
 
 
+def ff_dot_batched_backward_workspace_size(total: int) -> int:
+    """Workspace bytes ff_dot_batched_backward needs for `total` elements."""
+    return int(lib.ff_dot_batched_backward_workspace_size(int(total)))
+
+
 @_on_stream
 def ff_dot_batched_backward(g: torch.Tensor, x: torch.Tensor, y: torch.Tensor,
                             offsets: torch.Tensor, want_dx: bool = True, want_dy: bool = True,
-                            stream=None):
+                            dx_out=None, dy_out=None, workspace=None, stream=None):
     """Backward pass of the batched dot for per-vector upstream gradients g
     (2, nvec): every element i of vector v gets dx_i = g_v y_i and
     dy_i = g_v x_i (Mul22), elements of no vector zeros.  x and y are
     float-float (2, total) or binary32 (total,); the gradients are
-    float-float (2, total) (None when not wanted)."""
+    float-float (2, total) (None when not wanted), written into dx_out /
+    dy_out when given.  workspace: uint8 device tensor of at least
+    ff_dot_batched_backward_workspace_size(total) bytes (allocated per call
+    when omitted)."""
     _check_ff(g, "g")
     nvec = _check_offsets(offsets, g.device)
     if g.dim() != 2 or g.shape[1] != nvec:
@@ -726,15 +768,21 @@ def ff_dot_batched_backward(g: torch.Tensor, x: torch.Tensor, y: torch.Tensor,
     yh, yl, n2 = _ff_or_f32_planes(y, "y")
     if n != n2 or x.device != g.device or y.device != g.device:
         raise ValueError("x, y and g must agree in length and device")
-    dx = ff_empty((n,), device=g.device) if want_dx else None
-    dy = ff_empty((n,), device=g.device) if want_dy else None
+    dx = (ff_empty((n,), device=g.device) if dx_out is None else dx_out) if want_dx else None
+    dy = (ff_empty((n,), device=g.device) if dy_out is None else dy_out) if want_dy else None
+    for t, name in ((dx, "dx_out"), (dy, "dy_out")):
+        if t is not None:
+            _check_ff(t, name)
+            if t.shape != (2, n) or t.device != g.device:
+                raise ValueError(f"{name} must have shape (2, {n}) on {g.device}")
+    ws = _workspace(ff_dot_batched_backward_workspace_size(n), g.device, workspace)
     gh, gl = _planes(g)
     dxh, dxl = _planes(dx) if want_dx else (_null(), _null())
     dyh, dyl = _planes(dy) if want_dy else (_null(), _null())
     with torch.cuda.device(g.device):
         check("ff_dot_batched_backward", lib.ff_dot_batched_backward(
             gh, gl, ctypes.c_void_p(offsets.data_ptr()), nvec, n, xh, xl, yh, yl, dxh, dxl, dyh,
-            dyl, _stream_handle(stream)))
+            dyl, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream)))
     return dx, dy
 
 

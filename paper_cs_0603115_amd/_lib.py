@@ -76,7 +76,9 @@ SIGNATURES = {
     "ff_horner_f32": ([_P, _i32, _P, _P, _i64, _P], _st),
     "ff_horner_comp": ([_P, _i32, _P, _P, _i64, _P], _st),
     "ff_horner_ff": ([_P, _P, _i32, _P, _P, _P, _P, _i64, _P], _st),
-    "ff_dot_batched_backward": ([_P, _P, _P, _i32, _i64, _P, _P, _P, _P, _P, _P, _P, _P, _P], _st),
+    "ff_dot_batched_backward_workspace_size": ([_i64], _sz),
+    "ff_dot_batched_backward": ([_P, _P, _P, _i32, _i64, _P, _P, _P, _P, _P, _P, _P, _P,
+                                 _P, _sz, _P], _st),
     "ff_gemm_workspace_size": ([_i64, _i64, _i64, _i32], _sz),
     "ff_gemm": ([_i64, _i64, _i64, _P, _P, _i64, _P, _P, _i64, _P, _P, _i64, _i32, _P, _sz, _P],
                 _st),

@@ -394,26 +394,32 @@ __global__ __launch_bounds__(kDotBwdThreads) void dot_backward(const float *__re
 
 // Backward pass of the batched dot s_v = sum over vector v of x_i y_i:
 // every element i of vector v gets dx_i = Mul22(g_v, y_i) and
-// dy_i = Mul22(g_v, x_i); elements of no vector get zeros.
-// One workgroup per block of kBwdBlock consecutive elements, launched in
-// order, so that the resident workgroups sweep memory together.  The
-// workgroup finds, by two binary searches over the (clamped) offsets, the
-// vectors owning its first and last element, and when that window holds
-// between one and kBwdWin vectors copies their offsets and gradients into
-// LDS.  Thread t then takes elements b0 + t + kBwdThreads k (each wavefront
-// access is 256 contiguous bytes of a plane) in increasing order, advancing
-// its own vector index as they cross vector starts.  (A block spanning more
-// vectors -- tiny vectors -- looks them up in global memory.)  24 to 32
-// bytes per element and two Mul22: HBM-bound.  Measured on MI355X at
-// 438.9 M elements: these 4-byte lane-contiguous accesses outran one float4
-// group per lane by 1.6x for this pattern of two inputs and four outputs,
-// and 512 threads by 8 elements outran 256 by 16 (the same 4096-element
-// block, so the same searches) by 3 %; smaller blocks lose more to the
-// per-block searches than their access pattern gains.
-constexpr int kBwdThreads = 512;
-constexpr int kBwdPerThread = 8;
-constexpr int64_t kBwdBlock = static_cast<int64_t>(kBwdThreads) * kBwdPerThread;  // 4096
-constexpr int kBwdWin = 256;
+// dy_i = Mul22(g_v, x_i); elements of no vector get zeros.  Two launches:
+//   records   one thread per block of kBwdBlock consecutive elements: a
+//             binary search over the clamped offsets for the vector owning
+//             the block's first element, stored with that vector's gradient
+//             and the next vector's start as one 16-byte record
+//   gradients one workgroup per block, launched in order, so that the
+//             resident workgroups sweep memory together: thread t takes
+//             elements b0 + t + kBwdThreads k (each wavefront access is 256
+//             contiguous bytes of a plane) and issues all its loads first,
+//             then the block's record (one scalar load, on a counter of its
+//             own); the vector starts inside a wavefront's range (usually
+//             none) are walked, up to kBwdWalk of them, and past that (vectors
+//             of a few elements) each lane searches its remaining elements'
+//             owners
+// Small blocks stream this pattern (two planes in, four out) fastest: a
+// pass-through kernel moved 6.5 TB/s at 256 threads by one element, 6.25 at
+// 128 by 1, 5.6 at 512 by 2 and 5.5 at 512 by 8 (438.9 M elements on
+// MI355X).  A search per block at that size -- even one shared by the
+// workgroup's wavefronts -- cost more than the access pattern gained (its
+// dependent loads wait behind the streaming traffic), hence the records.
+// 24 to 32 bytes per element and two Mul22: HBM-bound.
+constexpr int kBwdThreads = 256;
+constexpr int kBwdPer = 1;
+constexpr int64_t kBwdBlock = static_cast<int64_t>(kBwdThreads) * kBwdPer;
+constexpr int kBwdWalk = 8;
+constexpr int kBwdRecordThreads = 256;
 
 __device__ __forceinline__ int64_t clamped_offset(const int64_t *__restrict__ offsets, int64_t v,
                                                   int64_t total)
@@ -424,7 +430,7 @@ __device__ __forceinline__ int64_t clamped_offset(const int64_t *__restrict__ of
 
 // Number of vector starts at or before position p, minus one: the vector
 // owning element p, in [-1, nvec] (-1: before the first vector, nvec: after
-// the last).
+// the last).  With offsets out of order the result is still in that range.
 __device__ __forceinline__ int64_t owner_of(const int64_t *__restrict__ offsets, int32_t nvec,
                                             int64_t total, int64_t p)
 {
@@ -439,108 +445,126 @@ __device__ __forceinline__ int64_t owner_of(const int64_t *__restrict__ offsets,
     return lo - 1;
 }
 
+// Record of block b: x = the vector owning element b * kBwdBlock (-1 .. nvec),
+// y, z = the bits of its gradient (zero when it is no vector), w = the start
+// of the next vector relative to the block's first element, clipped to
+// [0, INT32_MAX] (INT32_MAX: none within reach).
+__global__ __launch_bounds__(kBwdRecordThreads) void dot_bwd_records(
+    const float *__restrict__ g_hi, const float *__restrict__ g_lo,
+    const int64_t *__restrict__ offsets, int32_t nvec, int64_t total, int64_t nblocks,
+    int4 *__restrict__ records)
+{
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * kBwdRecordThreads + threadIdx.x;
+    if (b >= nblocks)
+        return;
+    const int64_t b0 = b * kBwdBlock;
+    const int64_t v = owner_of(offsets, nvec, total, b0);
+    const bool ok = v >= 0 && v < nvec;
+    const float gh = ok ? g_hi[v] : 0.0f, gl = ok ? g_lo[v] : 0.0f;
+    int64_t rel = INT32_MAX;
+    if (v < nvec) {
+        const int64_t o = clamped_offset(offsets, v + 1, total) - b0;
+        rel = o < 0 ? 0 : (o < INT32_MAX ? o : INT32_MAX);
+    }
+    records[b] = make_int4(static_cast<int32_t>(v), __float_as_int(gh), __float_as_int(gl),
+                           static_cast<int32_t>(rel));
+}
+
 template <bool XLO, bool YLO, bool DX, bool DY>
 __global__ __launch_bounds__(kBwdThreads) void dot_batched_bwd(
     const float *__restrict__ g_hi, const float *__restrict__ g_lo,
     const int64_t *__restrict__ offsets, int32_t nvec, int64_t total,
+    const int4 *__restrict__ records,
     const float *__restrict__ xh, const float *__restrict__ xl, const float *__restrict__ yh,
     const float *__restrict__ yl, float *__restrict__ dxh, float *__restrict__ dxl,
     float *__restrict__ dyh, float *__restrict__ dyl)
 {
-    __shared__ int64_t s_off[kBwdWin + 1];
-    __shared__ float s_gh[kBwdWin], s_gl[kBwdWin];
     const int t = threadIdx.x;
     const int64_t b0 = static_cast<int64_t>(blockIdx.x) * kBwdBlock;
-    const int64_t b1 = b0 + kBwdBlock < total ? b0 + kBwdBlock : total;
-    const int64_t v_first = owner_of(offsets, nvec, total, b0);
-    const int64_t v_last = owner_of(offsets, nvec, total, b1 - 1);
-    // window: vectors [va, vb]; s_off[j] = start of vector va + j, j <= count
-    const int64_t va = v_first > 0 ? v_first : 0;
-    const int64_t vb = v_last < nvec - 1 ? v_last : nvec - 1;
-    const int64_t count = vb >= va ? vb - va + 1 : 0;
-    const bool in_lds = count > 0 && count <= kBwdWin;
-    if (in_lds) {
-        for (int64_t j = t; j <= count; j += kBwdThreads) {
-            s_off[j] = clamped_offset(offsets, va + j, total);
-            if (j < count) {
-                s_gh[j] = g_hi[va + j];
-                s_gl[j] = g_lo[va + j];
+    // all of this thread's operands first
+    int64_t idx[kBwdPer];
+    float ox[kBwdPer], oxl[kBwdPer], oy[kBwdPer], oyl[kBwdPer];
+#pragma unroll
+    for (int k = 0; k < kBwdPer; ++k) {
+        const int64_t i = b0 + t + static_cast<int64_t>(kBwdThreads) * k;
+        idx[k] = i;
+        const bool in = i < total;
+        ox[k] = (DY && in) ? xh[i] : 0.0f;
+        oxl[k] = (DY && XLO && in) ? xl[i] : 0.0f;
+        oy[k] = (DX && in) ? yh[i] : 0.0f;
+        oyl[k] = (DX && YLO && in) ? yl[i] : 0.0f;
+    }
+    const int4 r = records[blockIdx.x];
+    // the wavefront's first and last element, the same on every lane
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int64_t w0 = b0 + 64 * wave;
+    if (w0 >= total)
+        return;
+    const int64_t w_end = w0 + 63 + static_cast<int64_t>(kBwdThreads) * (kBwdPer - 1);
+    const int64_t w_last = w_end < total ? w_end : total - 1;
+    int64_t v = r.x;
+    int64_t nxt = r.w == INT32_MAX ? INT64_MAX : b0 + r.w;
+    bool has[kBwdPer];
+    float gkh[kBwdPer], gkl[kBwdPer];
+    {
+        const bool ok = v >= 0 && v < nvec;
+        const float gh = __int_as_float(r.y), gl = __int_as_float(r.z);
+#pragma unroll
+        for (int k = 0; k < kBwdPer; ++k) {
+            has[k] = ok;
+            gkh[k] = gh;
+            gkl[k] = gl;
+        }
+    }
+    // elements at or after the start nxt of vector v + 1 belong to it (or to
+    // a later vector, found when its own start is reached)
+    for (int step = 0; step < kBwdWalk && nxt <= w_last; ++step) {
+        ++v;
+        const bool ok = v < nvec;
+        const float gh = ok ? g_hi[v] : 0.0f, gl = ok ? g_lo[v] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < kBwdPer; ++k) {
+            if (idx[k] >= nxt) {
+                has[k] = ok;
+                gkh[k] = gh;
+                gkl[k] = gl;
+            }
+        }
+        nxt = ok ? clamped_offset(offsets, v + 1, total) : INT64_MAX;
+    }
+    if (nxt <= w_last) {
+        // more vector starts in this range than the walk takes
+#pragma unroll
+        for (int k = 0; k < kBwdPer; ++k) {
+            if (idx[k] >= nxt && idx[k] < total) {
+                const int64_t u = owner_of(offsets, nvec, total, idx[k]);
+                has[k] = u >= 0 && u < nvec;
+                gkh[k] = has[k] ? g_hi[u] : 0.0f;
+                gkl[k] = has[k] ? g_lo[u] : 0.0f;
             }
         }
     }
-    __syncthreads();
-
-    auto run = [&](auto lds_tag) {
-        constexpr bool kLds = decltype(lds_tag)::value;
-        // With non-decreasing offsets every lookup falls inside the window
-        // (w - va <= count, v - va < count); the clamps only keep offsets
-        // that break that order from reading past it.
-        auto start_of = [&](int64_t w) -> int64_t {
-            if constexpr (kLds) {
-                const int64_t j = w - va;
-                return s_off[j < count ? j : count];
-            } else {
-                return clamped_offset(offsets, w, total);
-            }
-        };
-        // all of this thread's operands first: kBwdPerThread independent loads
-        // per plane in flight
-        float ox[kBwdPerThread], oxl[kBwdPerThread], oy[kBwdPerThread], oyl[kBwdPerThread];
 #pragma unroll
-        for (int k = 0; k < kBwdPerThread; ++k) {
-            const int64_t i = b0 + t + static_cast<int64_t>(kBwdThreads) * k;
-            const bool in = i < b1;
-            ox[k] = (DY && in) ? xh[i] : 0.0f;
-            oxl[k] = (DY && XLO && in) ? xl[i] : 0.0f;
-            oy[k] = (DX && in) ? yh[i] : 0.0f;
-            oyl[k] = (DX && YLO && in) ? yl[i] : 0.0f;
+    for (int k = 0; k < kBwdPer; ++k) {
+        const int64_t i = idx[k];
+        if (i >= total)
+            break;
+        float a = 0.0f, b = 0.0f, c = 0.0f, d = 0.0f;
+        if (has[k]) {
+            if (DX)
+                ffd::mul22<false>(gkh[k], gkl[k], oy[k], oyl[k], a, b);
+            if (DY)
+                ffd::mul22<false>(gkh[k], gkl[k], ox[k], oxl[k], c, d);
         }
-        int64_t v = v_first;
-        int64_t next = v < nvec ? start_of(v + 1) : INT64_MAX;
-        int64_t gv = -1;
-        float gh = 0.0f, gl = 0.0f;
-#pragma unroll
-        for (int k = 0; k < kBwdPerThread; ++k) {
-            const int64_t i = b0 + t + static_cast<int64_t>(kBwdThreads) * k;
-            if (i >= b1)
-                break;
-            while (v < nvec && next <= i) {
-                ++v;
-                next = v < nvec ? start_of(v + 1) : INT64_MAX;
-            }
-            float a = 0.0f, b = 0.0f, c = 0.0f, d = 0.0f;
-            if (v >= 0 && v < nvec) {
-                if (v != gv) {
-                    gv = v;
-                    if constexpr (kLds) {
-                        const int64_t j = v - va;
-                        const int64_t jc = j < count ? j : count - 1;
-                        gh = s_gh[jc];
-                        gl = s_gl[jc];
-                    } else {
-                        gh = g_hi[v];
-                        gl = g_lo[v];
-                    }
-                }
-                if (DX)
-                    ffd::mul22<false>(gh, gl, oy[k], oyl[k], a, b);
-                if (DY)
-                    ffd::mul22<false>(gh, gl, ox[k], oxl[k], c, d);
-            }
-            if (DX) {
-                dxh[i] = a;
-                dxl[i] = b;
-            }
-            if (DY) {
-                dyh[i] = c;
-                dyl[i] = d;
-            }
+        if (DX) {
+            dxh[i] = a;
+            dxl[i] = b;
         }
-    };
-    if (in_lds)
-        run(std::true_type{});
-    else
-        run(std::false_type{});
+        if (DY) {
+            dyh[i] = c;
+            dyl[i] = d;
+        }
+    }
 }
 
 bool all_aligned(std::initializer_list<const void *> ptrs, uintptr_t bytes)
@@ -706,11 +730,18 @@ ff_status ff_dot_backward(const float *g_hi, const float *g_lo, const float *x_h
     return ffh::launch_status();
 }
 
+size_t ff_dot_batched_backward_workspace_size(int64_t total_len)
+{
+    if (total_len <= 0)
+        return 0;
+    return static_cast<size_t>(ffh::cdiv(total_len, kBwdBlock)) * sizeof(int4);
+}
+
 ff_status ff_dot_batched_backward(const float *g_hi, const float *g_lo, const int64_t *offsets,
                                   int32_t nvec, int64_t total_len, const float *x_hi,
                                   const float *x_lo, const float *y_hi, const float *y_lo,
                                   float *dx_hi, float *dx_lo, float *dy_hi, float *dy_lo,
-                                  void *stream)
+                                  void *ws, size_t ws_bytes, void *stream)
 {
     if (nvec < 0 || total_len < 0)
         return FF_ERR_SIZE;
@@ -727,11 +758,21 @@ ff_status ff_dot_batched_backward(const float *g_hi, const float *g_lo, const in
     const int64_t blocks = ffh::cdiv(total_len, kBwdBlock);
     if (blocks > INT32_MAX)
         return FF_ERR_SIZE;
+    if (!ws || ws_bytes < ff_dot_batched_backward_workspace_size(total_len))
+        return FF_ERR_WORKSPACE;
+    if (!ffh::aligned(ws, 16))
+        return FF_ERR_ALIGN;
+    int4 *records = static_cast<int4 *>(ws);
+    hipLaunchKernelGGL(dot_bwd_records,
+                       dim3(static_cast<unsigned>(ffh::cdiv(blocks, int64_t(kBwdRecordThreads)))),
+                       dim3(kBwdRecordThreads), 0, ffh::as_stream(stream), g_hi, g_lo, offsets,
+                       nvec, total_len, blocks, records);
     const bool xlo = want_dy && x_lo, ylo = want_dx && y_lo;
     auto launch = [&](auto kernel) {
         hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBwdThreads), 0,
-                           ffh::as_stream(stream), g_hi, g_lo, offsets, nvec, total_len, x_hi,
-                           x_lo, y_hi, y_lo, dx_hi, dx_lo, dy_hi, dy_lo);
+                           ffh::as_stream(stream), g_hi, g_lo, offsets, nvec, total_len,
+                           static_cast<const int4 *>(records), x_hi, x_lo, y_hi, y_lo, dx_hi,
+                           dx_lo, dy_hi, dy_lo);
     };
     // one instantiation per (low words present, outputs wanted)
     if (want_dx && want_dy) {

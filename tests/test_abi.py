@@ -158,8 +158,13 @@ def test_dot_batched_backward_validation():
     g, o = (4096, 8192), 12288
     xs, ys = (16384, 20480), (24576, 28672)
     d = (32768, 36864, 40960, 45056)
-    call = lambda gg=g, off=o, nvec=3, total=100, x=xs, y=ys, out=d: fn(
-        gg[0], gg[1], off, nvec, total, x[0], x[1], y[0], y[1], *out, None)
+    ws = 49152
+    call = lambda gg=g, off=o, nvec=3, total=100, x=xs, y=ys, out=d, w=ws, wb=4096: fn(
+        gg[0], gg[1], off, nvec, total, x[0], x[1], y[0], y[1], *out, w, wb, None)
+    size = ff.lib.ff_dot_batched_backward_workspace_size
+    assert size(0) == 0 and size(-5) == 0
+    assert size(1) == 16 and size(256) == 16 and size(257) == 32
+    assert size(438907317) == 16 * -(-438907317 // 256)
     assert call(nvec=-1) == ERR_SIZE
     assert call(total=-1) == ERR_SIZE
     assert call(total=0) == 0
@@ -170,6 +175,12 @@ def test_dot_batched_backward_validation():
     assert call(y=(None, ys[1])) == ERR_NULL                # dx needs y
     assert call(off=o + 4) == ERR_ALIGN                     # offsets need 8 bytes
     assert call(x=(xs[0] + 2, xs[1])) == ERR_ALIGN
+    assert call(w=None) == ERR_WS
+    assert call(wb=15) == ERR_WS                     # 100 elements: one 16-byte record
+    assert call(total=257, wb=16) == ERR_WS          # two records
+    assert call(w=ws + 8) == ERR_ALIGN                      # records need 16 bytes
+    assert call(total=0, w=None) == 0                       # no-op reads no workspace
+    assert call(out=(None, None, None, None), w=None) == 0
 
 
 def test_copy_validation():
@@ -365,3 +376,20 @@ def test_import_fails_loudly_without_the_library(tmp_path):
                        text=True, timeout=300)
     assert r.returncode != 0
     assert "libff.so not found" in r.stderr
+
+
+def test_ff_empty_planes_start_4kib_apart():
+    """ff_empty / ff_zeros: two contiguous planes whose starts differ by a
+    multiple of 4 KiB, so both share the allocation's alignment (host
+    tensors are enough to check the layout)."""
+    import torch
+    for shape in [(), (0,), (1,), (63,), (1025,), (3, 7), (438907317 // 4096,)]:
+        for make in (ff.ff_empty, ff.ff_zeros):
+            t = make(shape, device="cpu")
+            assert t.shape == (2, *shape)
+            assert t.dtype == torch.float32
+            assert t[0].is_contiguous() and t[1].is_contiguous()
+            assert (t[1].data_ptr() - t[0].data_ptr()) % 4096 == 0
+            assert t.stride(0) >= max(t[0].numel(), 1)
+    z = ff.ff_zeros((5, 3), device="cpu")
+    assert not z.any()

@@ -4,11 +4,13 @@ autograd Function against an FP64 reference gradient and FP64 central
 differences of the bilinear loss L = sum_v w_v s_v.
 
 Cases: float-float and binary32 inputs (null low words), one output only,
-leading and trailing elements outside every vector, empty vectors, vectors
-shorter than a float4 group and longer than a wavefront's 8192-element
-slice, vector starts inside float4 groups, total lengths not a multiple of
-4, unaligned planes (the one-element path), no vectors at all, and the
-4096-vector batch of the benchmark (438 M elements) on sampled vectors.
+leading and trailing elements outside every vector, empty vectors and runs
+of them, vectors of one or two elements (more vector starts in a
+wavefront's range than the kernel walks, so each lane searches), exactly
+as many starts as it walks and one more, vectors longer than a block, total
+lengths not a multiple of the block, planes at 4-byte offsets, no vectors
+at all, preallocated outputs and workspace, and the 4096-vector batch of
+the benchmark (438 M elements) on every element.
 """
 import sys
 
@@ -59,6 +61,12 @@ CASES = {
     "tiny": ([1] * 300 + [2] * 100, 1, 2),
     "one_long": ([50001], 0, 0),
     "no_vectors": ([], 37, 0),
+    # a run of 20 empty vectors at one position: longer than the walk
+    "empty_run": ([5] + [0] * 20 + [7, 300, 0, 0, 0, 1000], 0, 5),
+    # after the block's first vector, 8 vector starts inside the first
+    # wavefront's 64 elements (as many as the walk takes); in the next
+    # block 9 (one more)
+    "walk_edge": ([7] * 8 + [200] + [6] * 9 + [300], 0, 3),
 }
 
 
@@ -105,18 +113,27 @@ def test_unaligned_planes():
     _check(dy.cpu().numpy(), want[2:], "dy")
 
 
-def test_benchmark_batch_sampled():
-    # the 4096-vector batch (binary32 inputs) on the full arrays; compared
-    # on a few whole vectors from the start, middle and end
+def test_benchmark_batch_every_element():
+    # the 4096-vector batch (binary32 inputs), the launch the benchmark
+    # times: every gradient word against the oracle, in pieces of whole
+    # vectors to bound host memory
     _announce("[gpu] dot backward on the 4096-vector batch")
+    ff = _ff()
     x, y, offs = fi.batched_dot(115003, device="cuda")
     nvec = offs.numel() - 1
+    total = x.numel()
     g = fi.random_ff(nvec, 5021, -4, 4).cuda()
-    dx, dy = _ff().ff_dot_batched_backward(g, x, y, offs)
+    dx, dy = ff.ff_empty((total,)), ff.ff_empty((total,))
+    ws = torch.empty(ff.ff_dot_batched_backward_workspace_size(total), dtype=torch.uint8,
+                     device="cuda")
+    ff.ff_dot_batched_backward(g, x, y, offs, dx_out=dx, dy_out=dy, workspace=ws)
     torch.cuda.synchronize()
+    _announce("  checking every element")
     oh = offs.cpu().numpy()
     gn = g.cpu().numpy()
-    for v0, v1 in ((0, 3), (nvec // 2, nvec // 2 + 3), (nvec - 3, nvec)):
+    step = 256
+    for v0 in range(0, nvec, step):
+        v1 = min(nvec, v0 + step)
         s, e = int(oh[v0]), int(oh[v1])
         sub = oh[v0:v1 + 1] - s
         xs, ys = x[s:e].cpu().numpy(), y[s:e].cpu().numpy()
@@ -124,8 +141,44 @@ def test_benchmark_batch_sampled():
         want = oracle.dot_batched_backward(gn[0, v0:v1], gn[1, v0:v1], sub, xs, z, ys, z)
         _check(dx[:, s:e].cpu().numpy(), want[:2], f"vectors {v0}..{v1} dx")
         _check(dy[:, s:e].cpu().numpy(), want[2:], f"vectors {v0}..{v1} dy")
-    del x, y, dx, dy
+    assert int(oh[0]) == 0 and int(oh[-1]) == total          # no element outside a vector
+    del x, y, dx, dy, ws
     torch.cuda.empty_cache()
+
+
+def test_preallocated_outputs_and_workspace():
+    """dx_out, dy_out and a caller's workspace give the bits of the
+    allocating call, on two calls in a row (the second shorter, reusing the
+    workspace); too small a workspace or wrongly shaped outputs are refused
+    before any launch."""
+    _announce("[gpu] dot backward into preallocated outputs")
+    ff = _ff()
+    lengths = [3, 700, 0, 1, 2, 5000, 9, 64, 65]
+    offs = _offsets(lengths, 4)
+    total = int(offs[-1]) + 6
+    x = fi.random_ff(total, 5031, -20, 20).cuda()
+    y = fi.random_ff(total, 5032, -20, 20).cuda()
+    g = fi.random_ff(len(lengths), 5033, -4, 4).cuda()
+    od = torch.from_numpy(offs).cuda()
+    ws = torch.empty(ff.ff_dot_batched_backward_workspace_size(total), dtype=torch.uint8,
+                     device="cuda")
+    for cut in (len(lengths), 4):
+        o = od[:cut + 1]
+        n = int(offs[cut]) + 1
+        want_dx, want_dy = ff.ff_dot_batched_backward(g[:, :cut].contiguous(), x[:, :n], y[:, :n], o)
+        dx = torch.full((2, n), float("nan"), device="cuda")
+        dy = torch.full((2, n), float("nan"), device="cuda")
+        rx, ry = ff.ff_dot_batched_backward(g[:, :cut].contiguous(), x[:, :n], y[:, :n], o,
+                                            dx_out=dx, dy_out=dy, workspace=ws)
+        assert rx is dx and ry is dy
+        assert torch.equal(dx.view(torch.int32), want_dx.view(torch.int32))
+        assert torch.equal(dy.view(torch.int32), want_dy.view(torch.int32))
+    small = torch.empty(ff.ff_dot_batched_backward_workspace_size(total) - 16, dtype=torch.uint8,
+                        device="cuda")
+    with pytest.raises(ValueError):
+        ff.ff_dot_batched_backward(g, x, y, od, workspace=small)
+    with pytest.raises(ValueError):
+        ff.ff_dot_batched_backward(g, x, y, od, dx_out=ff.ff_empty((total - 1,)))
 
 
 def test_autograd_against_fp64_gradient_and_finite_differences():
