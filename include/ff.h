@@ -209,8 +209,8 @@ ff_status ff_div_accurate(const float *a_hi, const float *a_lo,
  */
 
 /* Launch shape of the batched reductions.  Zero fields select the entry
- * point's default: 256 threads by 16 elements per thread for binary32
- * inputs (dots, sums, Dot2, Sum2), 256 by 8 for float-float inputs. */
+ * point's default: 256 threads by 32 elements per thread (chunks of 8192
+ * elements) for every input kind. */
 typedef struct ff_dot_cfg {
     int32_t block;  /* threads per workgroup: 64, 128, 256 or 512            */
     int32_t chunk;  /* elements per chunk: 0 or block * unroll (with unroll
@@ -222,8 +222,8 @@ typedef struct ff_dot_cfg {
 
 /* Bytes of device workspace the batched reductions need for nvec vectors
  * holding total_len elements in all, with this cfg (zero fields resolved
- * with the smallest default chunk, 2048, so that the size serves every
- * entry point).  Returns 0 for invalid arguments. */
+ * with the default chunk, 8192, which every entry point shares).  Returns 0
+ * for invalid arguments. */
 size_t ff_dot_batched_workspace_size(int64_t total_len, int32_t nvec,
                                      const ff_dot_cfg *cfg);
 
@@ -305,7 +305,7 @@ ff_status ff_sum2_batched(const float *x, const int64_t *offsets, int32_t nvec,
  * Limit: the batch's workspace (ff_dot_batched_workspace_size(total_len,
  * nvec, cfg), here resolved with ff_dot_batched's own defaults) must not
  * exceed FF_NOALLOC_SCRATCH_BYTES, otherwise FF_ERR_WORKSPACE (with the
- * default cfg, for example, 4096 vectors of up to 2.8e9 elements in all).
+ * default cfg, for example, 4096 vectors of up to 5.6e9 elements in all).
  * Nothing in the scratch needs to start at zero: every word a launch reads
  * was written earlier in the same call.  Every call on one device
  * shares that device's array, so calls that may overlap on one device (two

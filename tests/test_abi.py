@@ -276,9 +276,12 @@ def test_dot_noalloc_validation():
     assert call(ol=None) == ERR_NULL
     assert call(y=y + 2) == ERR_ALIGN
     assert call(offs=offs + 4) == ERR_ALIGN
-    # the batch must fit the static scratch: 16 MiB (default shape: 4096 elements
-    # per chunk)
+    # the batch must fit the static scratch: 16 MiB; 4096 vectors of up to
+    # 5.68e9 elements at the default shape (8192 elements per chunk), half as
+    # many at 4096 elements per chunk
     limit = 16 << 20
+    assert ff.ff_dot_batched_workspace_size(5_681_717_247, 4096) <= limit
+    assert ff.ff_dot_batched_workspace_size(5_681_717_248, 4096) > limit
     shape = (256, 4096, 0, 16)
     assert ff.ff_dot_batched_workspace_size(2_840_858_623, 4096, shape) <= limit
     assert ff.ff_dot_batched_workspace_size(2_840_858_623 + 4096, 4096, shape) > limit

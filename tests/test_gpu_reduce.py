@@ -36,7 +36,7 @@ def _announce(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def tree_depth(lengths, cfg, default=(256, 16)):
+def tree_depth(lengths, cfg, default=(256, 32)):
     """Longest chain of Add22s behind a result: a thread's `unroll` terms in
     order, the 6-level butterfly, the wavefronts of the workgroup in order,
     then the chunk partials lane-strided, a second butterfly, and slack.
