@@ -14,7 +14,7 @@
 //   combine   one wavefront per vector: Add22 of the vector's partials
 // The resident workgroups of the partials launch sweep memory together, the
 // pattern the HBM streams fastest (the elementwise operators' lesson): on
-// the 4096-vector batch it moved 0.80 of the HBM peak for all four input
+// the 4096-vector batch it moved 0.79-0.85 of the HBM peak for all four input
 // kinds and any placement of the planes, where persistent workers reducing
 // chunks spread over memory had reached 0.80 for binary32 dots but 0.60-0.75
 // for float-float inputs and sums.  Launch boundaries order the phases, so no
@@ -389,10 +389,6 @@ struct Cfg {
     int64_t chunk;
 };
 
-// Default launch shapes by input kind, from sweeps on the 4096-vector batch
-// (block 64-512 threads by 4-32 elements per thread): 256 by 16 for binary32
-// dots and sums (0.80 and 0.77-0.80 of HBM peak), 256 by 8 for float-float
-// inputs (0.79-0.80; four planes in flight per element).
 // Default launch shape, the fastest measured on MI355X for every input kind
 // on the 4096-vector batch (438.9 M elements): 256 threads by 32 elements
 // (chunks of 8192), 0.84 of the HBM peak for both dots and the float-float

@@ -185,6 +185,15 @@ def test_dot_backward_beyond_2p31():
     dx, dy = ff.ff_dot_batched_backward(g, x, x, torch.from_numpy(offs_h).cuda())
     idx = _sample_index(total, "cuda")
     dxs, dys = dx[:, idx].cpu().numpy(), dy[:, idx].cpu().numpy()
+    # every element, segment by segment: a vector's words are its g, the rest zero
+    bounds = [0] + [int(o) for o in offs_h] + [total]
+    for seg in range(len(bounds) - 1):
+        a, b = bounds[seg], bounds[seg + 1]
+        v = seg - 1
+        for plane in range(2):
+            want = float(g[plane, v]) if 0 <= v < len(lengths) else 0.0
+            for t in (dx, dy):
+                assert bool((t[plane, a:b] == want).all()), (seg, plane)
     del dx, dy
     _free()
     owner = np.searchsorted(offs_h, idx.cpu().numpy(), side="right") - 1
