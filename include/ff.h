@@ -404,7 +404,8 @@ ff_status ff_dot_backward(const float *g_hi, const float *g_lo,
  * caller-owned; it holds, per block of 256 elements, the vector owning the
  * block's first element with its gradient (written by a first launch, read
  * by the second), so it must not be shared by calls that may overlap.
- * Errors: FF_ERR_SIZE (nvec < 0, total_len < 0), FF_ERR_NULL, FF_ERR_ALIGN
+ * Errors: FF_ERR_SIZE (nvec < 0, total_len < 0, or total_len beyond
+ * (2^31 - 1) * 256), FF_ERR_NULL, FF_ERR_ALIGN
  * (offsets not 8-byte, a plane not 4-byte or ws not 16-byte aligned),
  * FF_ERR_WORKSPACE (ws NULL or too small), FF_ERR_HIP.
  * total_len = 0, or no output wanted, is a no-op (ws is not read). */
