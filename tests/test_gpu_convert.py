@@ -1,7 +1,7 @@
 """GPU parity of the binary64 <-> float-float conversions: every word bit
 for bit against the oracle, on wide exponent ranges (low words down to the
 subnormal range, signed zeros), ragged sizes, planes aligned to 4 or 8 bytes
-only and a 2^24-element run; infinities, NaN and values beyond the binary32
+only, a 2^24-element run and every element at the benchmark's 2^28; infinities, NaN and values beyond the binary32
 range on 16-byte aligned and unaligned planes; the Python short names are
 the same entry points."""
 import sys
@@ -47,6 +47,28 @@ def test_from_and_to_f64_bitexact(n):
     torch.cuda.synchronize()
     want = oracle.to_f64(pairs[0].numpy(), pairs[1].numpy())
     assert np.array_equal(back.cpu().numpy().view(np.uint64), want.view(np.uint64))
+
+
+def test_benchmark_size_every_element():
+    # N = 2^28, the benchmark's size and launch shape: wide-exponent binary64
+    # values (low words down to the subnormal range) to float-float and back,
+    # every word against the oracle
+    n = 1 << 28
+    print(f"[gpu] conversions at the benchmark size n={n}", file=sys.stderr, flush=True)
+    ff = _ff()
+    x = _f64(n, 2300)
+    xd = torch.from_numpy(x).cuda()
+    pair = ff.ff_from_f64(xd)
+    back = ff.ff_to_f64(pair)
+    torch.cuda.synchronize()
+    del xd
+    g, b = pair.cpu().numpy(), back.cpu().numpy()
+    del pair, back
+    torch.cuda.empty_cache()
+    hi, lo = oracle.from_f64(x)
+    assert same_bits(g[0], hi), mismatch_report(g[0], hi)
+    assert same_bits(g[1], lo), mismatch_report(g[1], lo)
+    assert np.array_equal(b.view(np.uint64), oracle.to_f64(hi, lo).view(np.uint64))
 
 
 def test_unaligned_planes_and_short_names():
