@@ -201,6 +201,31 @@ def test_dot_backward_elementwise(n):
             assert same_bits(got[0], rh) and same_bits(got[1], rl)
 
 
+def test_dot_backward_at_the_benchmark_size():
+    # the benchmark's launch: float-float x and y at N = 2^28 (seeds 115061,
+    # 115062), g = 0.75 + 2^-30, into preallocated outputs; every word
+    n = 1 << 28
+    _announce(f"[gpu] single-dot backward, n {n}")
+    ff = _ff()
+    x = fi.gaussian_ff((n,), 115061, device="cuda")
+    y = fi.gaussian_ff((n,), 115062, device="cuda")
+    g = torch.tensor([[0.75], [2.0 ** -30]], dtype=torch.float32, device="cuda")
+    dx, dy = ff.ff_empty((n,)), ff.ff_empty((n,))
+    ff.ff_dot_backward(g, x, y, dx_out=dx, dy_out=dy)
+    torch.cuda.synchronize()
+    piece = 1 << 24
+    gh, gl = np.full(piece, 0.75, np.float32), np.full(piece, 2.0 ** -30, np.float32)
+    for lo in range(0, n, piece):
+        sl = slice(lo, lo + piece)
+        for got, other in ((dx, y), (dy, x)):
+            o = other[:, sl].cpu().numpy()
+            rh, rl = oracle.mul22(gh, gl, o[0], o[1])
+            gn = got[:, sl].cpu().numpy()
+            assert same_bits(gn[0], rh) and same_bits(gn[1], rl), lo
+    del x, y, dx, dy
+    torch.cuda.empty_cache()
+
+
 def test_autograd_matvec_then_dot():
     ff = _ff()
     from paper_cs_0603115_amd.autograd import FFDot, FFMatVec, ff_one

@@ -174,6 +174,55 @@ def test_full_batch_4096_vectors():
     torch.cuda.empty_cache()
 
 
+def _check_exact(got, exact, absum, depth, label):
+    worst = -math.inf
+    for v in range(len(exact)):
+        err = abs(frac(got[0, v]) + frac(got[1, v]) - exact[v])
+        if absum[v] == 0:
+            assert err == 0, (label, v)
+            continue
+        assert err <= depth * TWO_M44 * absum[v] * (1 + Fraction(1, 1 << 20)), (label, v)
+        assert err <= TWO_M44 * absum[v], (label, v, float(err / absum[v]))
+        if err:
+            worst = max(worst, math.log2(err / absum[v]))
+    return worst
+
+
+def test_family_full_batch_as_benchmarked():
+    """The other entry points of the family on the 4096-vector batch, each at
+    its default shape, as the benchmark launches them: the float-float dot of
+    the values as (2, N) float-float vectors (zero low words, so its exact
+    value is the binary32 dot's), and the binary32 and float-float sums;
+    every vector against the exact value."""
+    _announce("[gpu] dot family at full size (4096 vectors)")
+    ff = _ff()
+    x, y, offs = fi.batched_dot(115003, device="cuda")
+    xf = torch.stack([x, torch.zeros_like(x)])
+    yf = torch.stack([y, torch.zeros_like(y)])
+    dot_ff = ff.ff_dot_ff_batched(xf, yf, offs).cpu().numpy()
+    del yf
+    sum_f32 = ff.ff_sum_batched(x, offs).cpu().numpy()
+    sum_ff = ff.ff_sum_ff_batched(xf, offs).cpu().numpy()
+    del xf
+    xn, yn, on = x.cpu().numpy(), y.cpu().numpy(), offs.cpu().numpy()
+    del x, y
+    torch.cuda.empty_cache()
+    depth = tree_depth(np.diff(on), (0, 0, 0, 0))
+    _announce("  exact dots")
+    exact = oracle.exact_dot_batched(xn, yn, on)
+    absum = oracle.exact_dot_batched(np.abs(xn), np.abs(yn), on)
+    w = _check_exact(dot_ff, exact, absum, depth, "ff_dot_ff_batched")
+    _announce(f"  ff-input dot worst normwise log2 error {w:.1f}")
+    del yn
+    _announce("  exact sums")
+    ones = np.ones_like(xn)
+    exact = oracle.exact_dot_batched(xn, ones, on)
+    absum = oracle.exact_dot_batched(np.abs(xn), ones, on)
+    for got, label in ((sum_f32, "ff_sum_batched"), (sum_ff, "ff_sum_ff_batched")):
+        w = _check_exact(got, exact, absum, depth, label)
+        _announce(f"  {label} worst normwise log2 error {w:.1f}")
+
+
 def test_batched_sums_binary32_and_float_float():
     _announce("[gpu] sum batched")
     ff = _ff()
