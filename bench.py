@@ -338,6 +338,27 @@ def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
             f"all {nall} vectors ({total} elements), sequential Add22 dot per vector, vectors "
             f"in {4 * th} pieces, C oracle on {th} host threads, {dtp:.2f} s (one thread: "
             f"first {nv} vectors, {e} elements, {dt:.2f} s)")
+        # the backward on the same batch: per-vector gradients (1, 0), as timed above
+        import numpy as np
+        g1, g0 = np.ones(nall, np.float32), np.zeros(nall, np.float32)
+        zs = np.zeros(e, np.float32)
+        dt = _oracle_timed(lambda: oracle.dot_batched_backward(
+            g1[:nv], g0[:nv], offs_h[:nv + 1], xa[:e], zs, ya[:e], zs))
+        del zs
+
+        def bpiece(v0, v1):
+            o0, o1 = int(offs_h[v0]), int(offs_h[v1])
+            z = np.zeros(o1 - o0, np.float32)
+            return lambda: oracle.dot_batched_backward(g1[v0:v1], g0[v0:v1],
+                                                       offs_h[v0:v1 + 1] - o0, xa[o0:o1], z,
+                                                       ya[o0:o1], z)
+
+        dtp, th = _oracle_parallel([bpiece(v0, v1) for v0, v1 in _chunks(nall, 4 * _host_threads())])
+        out["dot_batched"]["backward"]["cpu_baseline"] = _baseline(
+            total / dtp, th, e / dt, "elements/s",
+            f"all {nall} vectors ({total} elements), dx and dy by Mul22 per element, vectors "
+            f"in {4 * th} pieces, C oracle on {th} host threads, {dtp:.2f} s (one thread: "
+            f"first {nv} vectors, {e} elements, {dt:.2f} s)")
         del xa, ya
     del x, y, offs, res, ws
     torch.cuda.empty_cache()
@@ -434,6 +455,18 @@ def secondary(stream, cpu: bool = True, dot_cfg=None) -> dict:
         conv[name] = {"ms": round(ms, 4), "GB/s": round(gbs, 1),
                       "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     out["conversions_2p28"] = conv
+    if cpu:
+        import oracle
+        xh = xd.cpu().numpy()
+        m = 1 << 26
+        dt = _oracle_timed(lambda: oracle.from_f64(xh[:m]))
+        dtp, th = _oracle_parallel([lambda lo=lo, hi=hi: oracle.from_f64(xh[lo:hi])
+                                    for lo, hi in _chunks(n, 4 * _host_threads())])
+        conv["cpu_baseline"] = _baseline(
+            n / dtp, th, m / dt, "elements/s (binary64 to float-float)",
+            f"all {n} values in {4 * th} contiguous pieces, C oracle on {th} host threads, "
+            f"{dtp:.2f} s (one thread: first {m} values, {dt:.2f} s)")
+        del xh
     del xd, pair, back
     torch.cuda.empty_cache()
 
